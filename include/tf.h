@@ -1,0 +1,201 @@
+/*
+ * tf.h -- C ABI of the MI355X SALS / CDTF sparse tensor-factorisation path.
+ *
+ * Problem (Definition 1, eq. (TF) of Shin & Kang, arXiv:1410.5209): given the
+ * observed entries Omega of an N-way tensor X, a rank K and lambda > 0, find
+ * factor matrices A^(n) (I_n x K) minimising
+ *     sum_{Omega} (x - sum_k prod_n a^(n)_{i_n k})^2 + lambda sum_n ||A^(n)||_F^2.
+ * The library runs Algorithm 1 (serial SALS) on one GPU: one outer iteration
+ * walks the K columns in blocks of C, updating every row of every factor by
+ * eq. (SALS) and keeping the residual tensor R of eq. (SALS_R) up to date.
+ * C = 1 is CDTF; C = K with one inner iteration is ALS (eq. (ALS)).
+ *
+ * Conventions for every call:
+ *  - Every call returns tf_status (TF_OK = 0); no exception crosses the ABI.
+ *    tf_last_error() returns a message for the last failure on that context.
+ *  - "device" pointers are HIP device memory of the current device; "host"
+ *    pointers are ordinary host memory.  The caller keeps ownership of every
+ *    buffer it passes; the library copies what it needs and never frees them.
+ *  - Work runs on the stream given in tf_options (NULL = the null stream).
+ *    Calls that return values to the host synchronise that stream.
+ *  - A context is used by one host thread at a time, except the tf_serve_*
+ *    calls, which are thread-safe.
+ *  - Indices are 0-based int32; index tuples are row-major (entry j occupies
+ *    idx[j*N .. j*N+N-1]); factors are row-major I_n x K.
+ */
+#ifndef TF_SALS_H
+#define TF_SALS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tf_status;
+#define TF_OK 0
+#define TF_E_INVALID 1      /* an argument breaks a documented rule */
+#define TF_E_NOMEM 2        /* device or host allocation failed */
+#define TF_E_DEVICE 3       /* a HIP runtime call failed, or no GPU */
+#define TF_E_NUMERIC 4      /* a Cholesky pivot was not positive */
+#define TF_E_UNSUPPORTED 5  /* a valid request this build does not run */
+#define TF_E_BUSY 6         /* serving queue full */
+#define TF_E_STATE 7        /* call not allowed in the context's state */
+
+/* Arithmetic of the path. In every mode the C x C Cholesky solve and the
+ * loss reduction run in FP64. */
+#define TF_PREC_F64 0   /* factors, residual, Gram accumulation: FP64 */
+#define TF_PREC_F32 1   /* factors, residual, Gram accumulation: FP32 */
+#define TF_PREC_BF16 2  /* factors BF16 (round to nearest even); residual and
+                           Gram accumulation FP32 */
+
+/* How rows are mapped to the GPU in a mode pass. */
+#define TF_STRATEGY_PLAIN 0  /* one wavefront per non-empty row, in row order */
+#define TF_STRATEGY_SKEW 1   /* rows bucketed by length (1..64 lanes per row),
+                                rows above split_threshold cut into chunks whose
+                                partial Gram matrices are summed in a fixed order */
+
+typedef struct tf_options {
+    uint32_t size;             /* sizeof(tf_options): versions the struct */
+    int32_t precision;         /* TF_PREC_* (default TF_PREC_F32) */
+    int32_t reg_mode;          /* 0: lambda as in eq. (TF) (default);
+                                  1: weighted lambda, row i of mode n uses
+                                     lambda * |Omega^(n)_i| (Section 5.1.3) */
+    int32_t first_factor_zero; /* 1 (default): A^(1) = 0 so that R = X
+                                  (Section 3.1); 0: all factors random */
+    int32_t strategy;          /* TF_STRATEGY_* (default TF_STRATEGY_SKEW) */
+    uint64_t seed;             /* factor initialisation seed (default 2) */
+    void *stream;              /* hipStream_t, NULL = null stream */
+    int32_t lane_nnz;          /* SKEW: target nonzeros per lane (0 = 8) */
+    int32_t split_threshold;   /* SKEW: rows longer than this are split
+                                  (0 = 4096) */
+    int32_t chunk_nnz;         /* SKEW: nonzeros per chunk of a split row
+                                  (0 = 2048) */
+    int32_t slab_pad;          /* slab row stride alignment in bytes:
+                                  16 (default) or 64 */
+} tf_options;
+
+typedef struct tf_ctx tf_ctx;
+
+/* Fill *opt with the defaults above (size set). */
+void tf_default_options(tf_options *opt);
+
+/*
+ * tf_init -- build the model state from the observed entries.
+ *   N       modes, 2 <= N <= 8
+ *   dims    host[N], 1 <= I_n <= 2^31 - 1
+ *   nnz     number of observed entries, 1 <= nnz <= 2^31 - 1
+ *   d_idx   device, nnz x N int32 index tuples (row-major); the input order
+ *           defines the entry id j used by tf_get_residual and tf_get_csr.
+ *           A repeated tuple is one more loss term.
+ *   d_vals  device, nnz FP64 observed values
+ *   K       rank >= 1;  lambda > 0 (eq. (TF))
+ *   opt     NULL for defaults
+ * Builds, per mode, the CSR of the row sets Omega^(n)_i (Table 1) with a
+ * stable sort (entries keep their input order inside a row), the per-mode
+ * copies of the residual, and the row work plan; initialises the factors
+ * (SplitMix64 counters, U(0,1)/sqrt(K), A^(1) = 0 unless first_factor_zero
+ * is 0) and the residual r = x - reconstruction.  Synchronises the stream.
+ * Errors: TF_E_INVALID for a rule above, an index outside [0, I_n) or a
+ * non-finite value (the message names the first bad entry); TF_E_NOMEM;
+ * TF_E_DEVICE.  On error *out is NULL.
+ */
+tf_status tf_init(tf_ctx **out, int32_t N, const int64_t *dims, int64_t nnz,
+                  const int32_t *d_idx, const double *d_vals, int32_t K, double lambda,
+                  const tf_options *opt);
+
+/* Release everything the context owns.  NULL is a no-op. */
+void tf_destroy(tf_ctx *ctx);
+
+/* Message of the last failed call on ctx (owned by ctx; "" if none). */
+const char *tf_last_error(const tf_ctx *ctx);
+
+/*
+ * tf_sweep -- one outer iteration of Algorithm 1.  The current column order
+ * (tf_set_col_order; identity by default) is walked in ceil(K/C) blocks of C
+ * columns, the last block shorter when C does not divide K.  For each block:
+ * R-hat is formed, T_in inner iterations update every row of every mode by
+ * eq. (SALS) (FP64 Cholesky, text after Theorem 1), and R is brought up to
+ * date by eq. (SALS_R).  1 <= C <= min(K, 16); T_in >= 1.  Blocks until done.
+ * TF_E_NUMERIC: a pivot was not positive; the message names the mode and
+ * row, and the context must be restored with tf_set_factor + tf_resync.
+ * TF_E_STATE: factors were set without tf_resync.
+ */
+tf_status tf_sweep(tf_ctx *ctx, int32_t C, int32_t T_in);
+
+/*
+ * tf_split -- one block (split) of Algorithm 1 on the given columns:
+ * h_cols host[ncols], distinct, in [0, K), 1 <= ncols <= 16.  Same
+ * semantics and errors as one block of tf_sweep.
+ */
+tf_status tf_split(tf_ctx *ctx, int32_t ncols, const int32_t *h_cols, int32_t T_in);
+
+/* Column order used by tf_sweep: h_order host[K], a permutation of 0..K-1
+ * (Algorithm 1 picks columns without replacement; a fixed order is the
+ * paper's choice for CDTF, Section 3.1). */
+tf_status tf_set_col_order(tf_ctx *ctx, const int32_t *h_order);
+tf_status tf_get_col_order(const tf_ctx *ctx, int32_t *h_order);
+
+/*
+ * tf_loss -- eq. (TF) in FP64: sum of squared residuals plus lambda times
+ * the squared factor norms (weighted by row counts in reg_mode 1).
+ * *train_rmse = sqrt(sum r^2 / nnz).  Either output may be NULL.
+ */
+tf_status tf_loss(tf_ctx *ctx, double *loss, double *train_rmse);
+
+/*
+ * tf_predict -- x-hat = sum_k prod_n a^(n)_{i_n k} (the model of eq. (TF))
+ * for m query tuples.  d_idx device m x N int32; d_out device m FP64.
+ * TF_E_INVALID for an index out of range (nothing written).  m = 0 is a no-op.
+ */
+tf_status tf_predict(tf_ctx *ctx, int64_t m, const int32_t *d_idx, double *d_out);
+
+/* Factor n as FP64 (host[I_n x K]); set marks the residual stale until
+ * tf_resync.  Values are rounded to the storage precision. */
+tf_status tf_get_factor(tf_ctx *ctx, int32_t n, double *h);
+tf_status tf_set_factor(tf_ctx *ctx, int32_t n, const double *h);
+
+/* r = x - reconstruction recomputed from the current factors (definition
+ * of R, Section 3.1). */
+tf_status tf_resync(tf_ctx *ctx);
+
+/* The maintained residual r, host[nnz] FP64, in input order. */
+tf_status tf_get_residual(tf_ctx *ctx, double *h);
+
+/* Mode-n CSR: h_rowptr host[I_n + 1], h_perm host[nnz] (entry ids). */
+tf_status tf_get_csr(tf_ctx *ctx, int32_t n, int64_t *h_rowptr, int32_t *h_perm);
+
+/* ------------------------------------------------------------------ */
+/* Kernel timing: HIP events around every launch of the row-accumulation
+ * kernel (the one that gathers factor rows and builds the Gram matrices). */
+typedef struct tf_kstats {
+    int64_t launches;       /* accumulation launches timed */
+    double total_ms;        /* summed event time */
+    double alg_bytes;       /* summed algorithmic bytes of those launches */
+    int64_t sweeps;
+} tf_kstats;
+tf_status tf_profile(tf_ctx *ctx, int32_t enable);        /* 1 on, 0 off; resets */
+tf_status tf_profile_read(tf_ctx *ctx, tf_kstats *out);    /* synchronises */
+
+/* ------------------------------------------------------------------ */
+/* Host-only row planner (no GPU needed): classifies the rows of one mode
+ * from its CSR offsets, as tf_init does for every mode.
+ *   rowptr host[I + 1]; strategy, lane_nnz, split_threshold, chunk_nnz as in
+ *   tf_options.  Outputs counts: tasks (wavefront work units), split rows and
+ *   chunks, and per-G row counts hist[7] for G = 1,2,4,...,64 lanes per row.
+ */
+typedef struct tf_plan_summary {
+    int64_t tasks;
+    int64_t split_rows;
+    int64_t chunks;
+    int64_t empty_rows;
+    int64_t rows_by_lanes[7];
+} tf_plan_summary;
+tf_status tf_plan_rows(const int64_t *rowptr, int64_t I, int32_t strategy, int32_t lane_nnz,
+                       int32_t split_threshold, int32_t chunk_nnz, tf_plan_summary *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TF_SALS_H */

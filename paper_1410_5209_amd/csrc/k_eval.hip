@@ -1,0 +1,226 @@
+// Residual evaluation on the mode copies, the loss of eq. (TF), the
+// stand-alone residual update of a split boundary, and prediction
+// (arXiv:1410.5209: eq. (TF), eq. (SALS_R), R-hat of Algorithm 1).
+//
+// The mode copies hold R-hat of the last split (x minus every column outside
+// that split), so the true residual is r = rhat - sum_{c in last split}
+// prod_n a^(n) (eq. (SALS_R)); every kernel here forms it on the fly.
+// Reductions are deterministic: fixed work per block, fixed trees.
+#include "dev_common.h"
+
+namespace tfk {
+
+// Row slot of this lane in a task (same mapping as the accumulation kernel).
+struct Slot {
+    int row;
+    int64_t beg, end;
+    int G, sub;
+};
+
+__device__ __forceinline__ Slot task_slot(const Task *tasks, const int32_t *items,
+                                          const Chunk *chunks, const int32_t *rowptr, int t,
+                                          int lane)
+{
+    const Task task = tasks[t];
+    Slot s;
+    s.G = task.G;
+    const int lg = __ffs(task.G) - 1;
+    const int grp = lane >> lg;
+    s.sub = lane & (task.G - 1);
+    s.row = -1;
+    s.beg = s.end = 0;
+    if (task.kind == 0) {
+        if (grp < task.count) {
+            s.row = items[task.base + grp];
+            s.beg = rowptr[s.row];
+            s.end = rowptr[s.row + 1];
+        }
+    } else {
+        const Chunk c = chunks[task.base];
+        s.row = c.row;
+        s.beg = c.beg;
+        s.end = c.end;
+    }
+    return s;
+}
+
+__device__ __forceinline__ double block_sum_256(double v)
+{
+    __shared__ double ws[4];
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+    __syncthreads();
+    return s;
+}
+
+// Sum of r^2 over the mode-0 copy (per block), optionally writing r in input order.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_eval_resid(EvalArgs a)
+{
+    using TS = typename Types<PREC>::TS;
+    using TR = typename Types<PREC>::TR;
+    const int lane = threadIdx.x & 63;
+    const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+    double se = 0.0;
+    if (t < a.ntasks) {
+        const Slot s = task_slot(a.tasks, a.items, a.chunks, a.rowptr, t, lane);
+        const TR *rh = reinterpret_cast<const TR *>(a.rhat);
+        for (int64_t j = s.beg + s.sub; j < s.end; j += s.G) {
+            double r = (double)rh[j];
+            for (int c = 0; c < a.npend; ++c) {
+                double prod = load_f64(reinterpret_cast<const TS *>(a.Pown) + (int64_t)s.row * a.ld + c);
+                for (int l = 0; l < a.no; ++l)
+                    prod *= load_f64(reinterpret_cast<const TS *>(a.P[l]) + (int64_t)a.oidx[l][j] * a.ld + c);
+                r -= prod;
+            }
+            se += r * r;
+            if (a.r_out) a.r_out[a.perm[j]] = r;
+        }
+    }
+    const double tot = block_sum_256(se);
+    if (threadIdx.x == 0) a.partials[blockIdx.x] = tot;
+}
+
+hipError_t launch_eval_residual(int prec, const EvalArgs &a, int grid, hipStream_t st)
+{
+    if (prec == P_F64) hipLaunchKernelGGL(k_eval_resid<P_F64>, dim3(grid), dim3(256), 0, st, a);
+    else if (prec == P_F32) hipLaunchKernelGGL(k_eval_resid<P_F32>, dim3(grid), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(k_eval_resid<P_BF16>, dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+// Split boundary on one mode copy, not fused into a row pass (used when the
+// previous split had more columns than the current row kernel carries):
+// rhat <- (rhat - sum_{pending c} prod_n P) + sum_{current c} prod_n S,
+// every factor value taken at the start of the split.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_sync(AccumArgs a, int npend, int ncur)
+{
+    using TS = typename Types<PREC>::TS;
+    using TR = typename Types<PREC>::TR;
+    using TA = typename Types<PREC>::TA;
+    const int lane = threadIdx.x & 63;
+    const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= a.ntasks) return;
+    const Slot s = task_slot(a.tasks, a.items, a.chunks, a.rowptr, t, lane);
+    TR *rh = reinterpret_cast<TR *>(a.rhat);
+    const TS *Pown = reinterpret_cast<const TS *>(a.Pown) + (int64_t)s.row * a.ld;
+    const TS *Sown = reinterpret_cast<const TS *>(a.Sown) + (int64_t)s.row * a.ld;
+    for (int64_t j = s.beg + s.sub; j < s.end; j += s.G) {
+        TA dr = TA(0), ds = TA(0);
+        for (int c = 0; c < npend; ++c) {
+            TA prod = (TA)load_f64(Pown + c);
+            for (int l = 0; l < a.no; ++l)
+                prod *= (TA)load_f64(reinterpret_cast<const TS *>(a.P[l]) + (int64_t)a.oidx[l][j] * a.ld + c);
+            dr += prod;
+        }
+        for (int c = 0; c < ncur; ++c) {
+            TA prod = (TA)load_f64(Sown + c);
+            for (int l = 0; l < a.no; ++l)
+                prod *= (TA)load_f64(reinterpret_cast<const TS *>(a.S[l]) + (int64_t)a.oidx[l][j] * a.ld + c);
+            ds += prod;
+        }
+        rh[j] = (TR)(((TA)rh[j] - dr) + ds);
+    }
+}
+
+hipError_t sync_copy(int prec, const AccumArgs &a, int npend, int ncur, int grid, hipStream_t st)
+{
+    if (prec == P_F64) hipLaunchKernelGGL(k_sync<P_F64>, dim3(grid), dim3(256), 0, st, a, npend, ncur);
+    else if (prec == P_F32) hipLaunchKernelGGL(k_sync<P_F32>, dim3(grid), dim3(256), 0, st, a, npend, ncur);
+    else hipLaunchKernelGGL(k_sync<P_BF16>, dim3(grid), dim3(256), 0, st, a, npend, ncur);
+    return hipGetLastError();
+}
+
+// Per-block sums of w_i * ||a_i||^2 (w_i = 1, or the row count when weighted).
+template <int PREC>
+__global__ __launch_bounds__(256) void k_reg(const void *A, int64_t I, int K, const int32_t *rowptr,
+                                             int weighted, double *partials)
+{
+    using TS = typename Types<PREC>::TS;
+    const int64_t per = (I + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * per;
+    const int64_t r1 = r0 + per < I ? r0 + per : I;
+    double acc = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        double s = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const double v = load_f64(reinterpret_cast<const TS *>(A) + i * K + k);
+            s += v * v;
+        }
+        const double w = weighted ? (double)(rowptr[i + 1] - rowptr[i]) : 1.0;
+        acc += w * s;
+    }
+    const double tot = block_sum_256(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+hipError_t reg_partials(int prec, const void *A, int64_t I, int K, const int32_t *rowptr,
+                        int weighted, double *partials, int nblocks, hipStream_t st)
+{
+    if (prec == P_F64) hipLaunchKernelGGL(k_reg<P_F64>, dim3(nblocks), dim3(256), 0, st, A, I, K, rowptr, weighted, partials);
+    else if (prec == P_F32) hipLaunchKernelGGL(k_reg<P_F32>, dim3(nblocks), dim3(256), 0, st, A, I, K, rowptr, weighted, partials);
+    else hipLaunchKernelGGL(k_reg<P_BF16>, dim3(nblocks), dim3(256), 0, st, A, I, K, rowptr, weighted, partials);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_sum(const double *p, int64_t n, double *out)
+{
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += p[i];
+    const double tot = block_sum_256(s);
+    if (threadIdx.x == 0) *out = tot;
+}
+
+hipError_t sum_partials(const double *partials, int64_t n, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, st, partials, n, out);
+    return hipGetLastError();
+}
+
+struct PredPtrs { const void *A[kMaxModes]; int64_t dims[kMaxModes]; };
+
+// x-hat = sum_k prod_n a^(n)_{i_n k}; one thread per query.
+template <int PREC>
+__global__ void k_predict(int N, int K, PredPtrs F, const int32_t *q, int64_t m, double *out,
+                          unsigned long long *bad)
+{
+    using TS = typename Types<PREC>::TS;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    int32_t ix[kMaxModes];
+    bool okq = true;
+    for (int n = 0; n < N; ++n) {
+        ix[n] = q[t * N + n];
+        okq = okq && ix[n] >= 0 && (int64_t)ix[n] < F.dims[n];
+    }
+    if (!okq) {
+        atomicMin(bad, (unsigned long long)t);
+        return;
+    }
+    double s = 0.0;
+    for (int k = 0; k < K; ++k) {
+        double prod = 1.0;
+        for (int n = 0; n < N; ++n)
+            prod *= load_f64(reinterpret_cast<const TS *>(F.A[n]) + (int64_t)ix[n] * K + k);
+        s += prod;
+    }
+    out[t] = s;
+}
+
+hipError_t launch_predict(int prec, int N, int K, const void *const *A, const int64_t *dims,
+                          const int32_t *q, int64_t m, double *out, unsigned long long *bad,
+                          hipStream_t st)
+{
+    PredPtrs F{};
+    for (int n = 0; n < N; ++n) { F.A[n] = A[n]; F.dims[n] = dims[n]; }
+    const int64_t grid = (m + 255) / 256;
+    if (prec == P_F64) hipLaunchKernelGGL(k_predict<P_F64>, dim3((unsigned)grid), dim3(256), 0, st, N, K, F, q, m, out, bad);
+    else if (prec == P_F32) hipLaunchKernelGGL(k_predict<P_F32>, dim3((unsigned)grid), dim3(256), 0, st, N, K, F, q, m, out, bad);
+    else hipLaunchKernelGGL(k_predict<P_BF16>, dim3((unsigned)grid), dim3(256), 0, st, N, K, F, q, m, out, bad);
+    return hipGetLastError();
+}
+
+}  // namespace tfk

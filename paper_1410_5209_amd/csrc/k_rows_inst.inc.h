@@ -1,0 +1,54 @@
+// Instantiates the row kernels of one precision (TF_PREC_ID) for its compute
+// widths (TF_CP_LIST) and every number of other modes (1..7).
+#pragma once
+
+#include "k_rows.inc.h"
+
+namespace tfk {
+
+template <int PREC, int CP, int NO>
+static hipError_t accum_no(bool first, const AccumArgs &a, int grid, hipStream_t st)
+{
+    if (first)
+        hipLaunchKernelGGL((k_accum<PREC, CP, NO, true>), dim3(grid), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_accum<PREC, CP, NO, false>), dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int PREC, int CP>
+static hipError_t accum_cp(int no, bool first, const AccumArgs &a, int grid, hipStream_t st)
+{
+    switch (no) {
+    case 1: return accum_no<PREC, CP, 1>(first, a, grid, st);
+    case 2: return accum_no<PREC, CP, 2>(first, a, grid, st);
+    case 3: return accum_no<PREC, CP, 3>(first, a, grid, st);
+    case 4: return accum_no<PREC, CP, 4>(first, a, grid, st);
+    case 5: return accum_no<PREC, CP, 5>(first, a, grid, st);
+    case 6: return accum_no<PREC, CP, 6>(first, a, grid, st);
+    case 7: return accum_no<PREC, CP, 7>(first, a, grid, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int PREC, int CP>
+static hipError_t solve_cp(const SolveArgs &a, hipStream_t st)
+{
+    const int grid = (int)((a.I + 255) / 256);
+    hipLaunchKernelGGL((k_solve<PREC, CP>), dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int PREC, int CP>
+static hipError_t reduce_cp(const int32_t *rows, const int32_t *ptr, int nsplit, const void *gpart,
+                            void *gram, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_chunk_reduce<PREC, CP>), dim3(nsplit), dim3(256), 0, st, rows, ptr,
+                       gpart, gram);
+    return hipGetLastError();
+}
+
+}  // namespace tfk
+
+#define TF_CP_CASE(FN, CPV, ...) \
+    case CPV: return FN<TF_PREC_ID, CPV>(__VA_ARGS__);

@@ -1,0 +1,802 @@
+// C ABI of the SALS / CDTF GPU path: context construction, the split driver
+// of Algorithm 1 (arXiv:1410.5209), loss, prediction and state access.
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "tf_internal.h"
+
+using namespace tfk;
+
+namespace tfk {
+hipError_t launch_accum_f64(int CP, int no, bool first, const AccumArgs &a, int grid, hipStream_t st);
+hipError_t launch_accum_f32(int CP, int no, bool first, const AccumArgs &a, int grid, hipStream_t st);
+hipError_t launch_accum_bf16(int CP, int no, bool first, const AccumArgs &a, int grid, hipStream_t st);
+hipError_t launch_solve_f64(int CP, const SolveArgs &a, hipStream_t st);
+hipError_t launch_solve_f32(int CP, const SolveArgs &a, hipStream_t st);
+hipError_t launch_solve_bf16(int CP, const SolveArgs &a, hipStream_t st);
+hipError_t launch_reduce_f64(int CP, const int32_t *, const int32_t *, int, const void *, void *, hipStream_t);
+hipError_t launch_reduce_f32(int CP, const int32_t *, const int32_t *, int, const void *, void *, hipStream_t);
+hipError_t launch_reduce_bf16(int CP, const int32_t *, const int32_t *, int, const void *, void *, hipStream_t);
+
+hipError_t launch_accum(int prec, int CP, int no, bool first, const AccumArgs &a, int grid, hipStream_t st)
+{
+    if (prec == P_F64) return launch_accum_f64(CP, no, first, a, grid, st);
+    if (prec == P_F32) return launch_accum_f32(CP, no, first, a, grid, st);
+    return launch_accum_bf16(CP, no, first, a, grid, st);
+}
+hipError_t launch_solve(int prec, int CP, const SolveArgs &a, hipStream_t st)
+{
+    if (prec == P_F64) return launch_solve_f64(CP, a, st);
+    if (prec == P_F32) return launch_solve_f32(CP, a, st);
+    return launch_solve_bf16(CP, a, st);
+}
+hipError_t launch_chunk_reduce(int prec, int CP, const int32_t *rows, const int32_t *ptr, int nsplit,
+                               const void *gpart, void *gram, hipStream_t st)
+{
+    if (prec == P_F64) return launch_reduce_f64(CP, rows, ptr, nsplit, gpart, gram, st);
+    if (prec == P_F32) return launch_reduce_f32(CP, rows, ptr, nsplit, gpart, gram, st);
+    return launch_reduce_bf16(CP, rows, ptr, nsplit, gpart, gram, st);
+}
+}  // namespace tfk
+
+namespace {
+
+thread_local std::string g_init_err;
+
+size_t ts_size(int prec) { return prec == P_F64 ? 8 : (prec == P_F32 ? 4 : 2); }
+size_t tr_size(int prec) { return prec == P_F64 ? 8 : 4; }
+size_t ta_size(int prec) { return prec == P_F64 ? 8 : 4; }
+int vec_w(int prec) { return (int)(16 / ts_size(prec)); }
+
+tf_status set_err(std::string *dst, tf_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    *dst = buf;
+    return s;
+}
+
+#define CTX_FAIL(ctx, s, ...) set_err(&(ctx)->err, (s), __VA_ARGS__)
+#define HIPCHK(ctx, call)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return CTX_FAIL(ctx, TF_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+hipError_t dalloc(T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc((void **)p, count * sizeof(T));
+}
+
+void dfree(void *p)
+{
+    if (p) (void)hipFree(p);
+}
+
+int key_bits_for(int64_t I)
+{
+    int b = 1;
+    while (b < 31 && ((int64_t)1 << b) < I) ++b;
+    return b;
+}
+
+// Ensure the Gram buffers hold records of compute width CP.
+tf_status ensure_gram(tf_ctx *c, int CP)
+{
+    if (CP <= c->slab_cp && c->gram) return TF_OK;
+    dfree(c->gram);
+    dfree(c->gpart);
+    c->gram = c->gpart = nullptr;
+    int64_t maxI = 0, maxch = 1;
+    for (int n = 0; n < c->N; ++n) {
+        maxI = std::max<int64_t>(maxI, c->m[n].I);
+        maxch = std::max<int64_t>(maxch, c->m[n].nchunks);
+    }
+    const size_t rec = (size_t)gram_stride(CP) * ta_size(c->prec);
+    HIPCHK(c, hipMalloc(&c->gram, (size_t)maxI * rec));
+    HIPCHK(c, hipMalloc(&c->gpart, (size_t)maxch * rec));
+    c->slab_cp = CP;
+    return TF_OK;
+}
+
+int64_t slab_ld(const tf_ctx *c, int width)
+{
+    const int vw = vec_w(c->prec);
+    int64_t ld = (width + vw - 1) / vw * vw;
+    if (c->opt.slab_pad == 64) {
+        const int64_t per = 64 / (int64_t)ts_size(c->prec);
+        ld = (ld + per - 1) / per * per;
+    }
+    return ld;
+}
+
+int64_t slab_cap_elems(const tf_ctx *c)
+{
+    // widest slab row: kMaxC columns, padded to 64 bytes
+    const int64_t per = 64 / (int64_t)ts_size(c->prec);
+    const int64_t w = (kMaxC + per - 1) / per * per;
+    return std::max<int64_t>(w, kMaxC);
+}
+
+void fill_accum_args(tf_ctx *c, int n, int npend, AccumArgs *a)
+{
+    std::memset(a, 0, sizeof *a);
+    auto &md = c->m[n];
+    a->rowptr = md.rowptr;
+    a->tasks = md.tasks;
+    a->ntasks = md.ntasks;
+    a->items = md.items;
+    a->chunks = md.chunks;
+    a->rhat = md.rhat;
+    int t = 0;
+    for (int l = 0; l < c->N; ++l) {
+        if (l == n) continue;
+        a->oidx[t] = md.oidx[t];
+        a->W[t] = c->m[l].W;
+        a->S[t] = c->m[l].S;
+        a->P[t] = c->m[l].P;
+        a->before[t] = l < n ? 1 : 0;
+        ++t;
+    }
+    a->Sown = md.S;
+    a->Pown = md.P;
+    a->has_pend = npend > 0 ? 1 : 0;
+    a->no = c->N - 1;
+    a->ld = c->ld;
+    a->gram = c->gram;
+    a->gpart = c->gpart;
+}
+
+hipEvent_t take_event(tf_ctx *c)
+{
+    if (!c->ev_free.empty()) {
+        hipEvent_t e = c->ev_free.back();
+        c->ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Algorithmic bytes of one accumulation launch (design-neutral byte model:
+// every index, residual and gathered factor element read once per use, no
+// cache credit).  Row pass: per entry 4(N-1) index bytes, one residual read,
+// (N-1) C factor elements; per row one offset.  The first pass of a split
+// also carries 1/N of the split's residual work (R-hat and eq. (SALS_R) done
+// once on a single residual array: per entry 4N index bytes, a residual read
+// and write, N (C_prev + C) factor elements).
+double alg_bytes(const tf_ctx *c, int n, int C, int npend, bool first)
+{
+    const double N = c->N, sf = (double)ts_size(c->prec), sr = (double)tr_size(c->prec);
+    const double nnz = (double)c->nnz;
+    double b = nnz * (4.0 * (N - 1) + sr + (N - 1) * C * sf) + 4.0 * (double)(c->m[n].I + 1);
+    if (first) b += nnz * (4.0 * N + 2.0 * sr + N * (npend + C) * sf) / N;
+    return b;
+}
+
+tf_status pack_all(tf_ctx *c, const int32_t *d_cols, int ncols, int width, bool into_p)
+{
+    for (int l = 0; l < c->N; ++l) {
+        auto &md = c->m[l];
+        hipError_t e = into_p
+            ? pack_slab(c->prec, md.A, md.I, c->K, d_cols, ncols, width, c->ld, md.P, nullptr, c->stream)
+            : pack_slab(c->prec, md.A, md.I, c->K, d_cols, ncols, width, c->ld, md.S, md.W, c->stream);
+        if (e != hipSuccess) return CTX_FAIL(c, TF_E_DEVICE, "pack: %s", hipGetErrorString(e));
+    }
+    return TF_OK;
+}
+
+// Upload the current columns (offset 0) and the pending columns (offset K).
+tf_status upload_cols(tf_ctx *c, const int32_t *cols, int ncols)
+{
+    std::vector<int32_t> h(2 * (size_t)c->K + 2, 0);
+    for (int q = 0; q < ncols; ++q) h[q] = cols[q];
+    for (size_t q = 0; q < c->pend.size(); ++q) h[c->K + q] = c->pend[q];
+    HIPCHK(c, hipMemcpyAsync(c->d_cols, h.data(), h.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));  // h is a stack buffer
+    return TF_OK;
+}
+
+// One split of Algorithm 1 on columns cols[0..ncols).
+tf_status run_split(tf_ctx *c, const int32_t *cols, int ncols, int T_in)
+{
+    const int CP = pick_cp(ncols, c->prec);
+    if (CP < 0) return CTX_FAIL(c, TF_E_UNSUPPORTED, "C = %d exceeds %d columns per split", ncols, kMaxC);
+    tf_status s = ensure_gram(c, CP);
+    if (s != TF_OK) return s;
+    const int npend = (int)c->pend.size();
+    const bool fuse = npend <= CP;
+    const int width = std::max(CP, npend);
+    c->ld = slab_ld(c, width);
+    if ((s = upload_cols(c, cols, ncols)) != TF_OK) return s;
+    const int32_t *d_cur = c->d_cols;
+    const int32_t *d_pend = c->d_cols + c->K;
+
+    // slabs at the start of the split: S (snapshot) and W (working copy) hold
+    // the split's columns, P the previous split's columns (final values)
+    if ((s = pack_all(c, d_cur, ncols, width, false)) != TF_OK) return s;
+    if (npend > 0 && (s = pack_all(c, d_pend, npend, width, true)) != TF_OK) return s;
+
+    if (!fuse) {  // bring every copy to R-hat of this split before the passes
+        for (int n = 0; n < c->N; ++n) {
+            AccumArgs a;
+            fill_accum_args(c, n, npend, &a);
+            const int grid = (c->m[n].ntasks + 3) / 4;
+            if (grid > 0) HIPCHK(c, sync_copy(c->prec, a, npend, ncols, grid, c->stream));
+        }
+    }
+
+    for (int it = 0; it < T_in; ++it) {
+        for (int n = 0; n < c->N; ++n) {
+            auto &md = c->m[n];
+            const bool first = fuse && it == 0;
+            AccumArgs a;
+            fill_accum_args(c, n, first ? npend : 0, &a);
+            const int grid = (md.ntasks + 3) / 4;
+            if (grid > 0) {
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                if (c->profiling) {
+                    e0 = take_event(c);
+                    e1 = take_event(c);
+                    if (e0) HIPCHK(c, hipEventRecord(e0, c->stream));
+                }
+                HIPCHK(c, launch_accum(c->prec, CP, c->N - 1, first, a, grid, c->stream));
+                if (c->profiling && e0 && e1) {
+                    HIPCHK(c, hipEventRecord(e1, c->stream));
+                    c->ev_pending.push_back(
+                        tf_ctx::Timed{e0, e1, alg_bytes(c, n, ncols, npend, first)});
+                }
+            }
+            if (md.nsplit > 0)
+                HIPCHK(c, launch_chunk_reduce(c->prec, CP, md.split_rows, md.split_chunk_ptr,
+                                              md.nsplit, c->gpart, c->gram, c->stream));
+            SolveArgs sa;
+            sa.rowptr = md.rowptr;
+            sa.I = md.I;
+            sa.gram = c->gram;
+            sa.W = md.W;
+            sa.ld = c->ld;
+            sa.lambda = c->lambda;
+            sa.reg_mode = c->opt.reg_mode;
+            sa.bad = c->d_bad + n;
+            HIPCHK(c, launch_solve(c->prec, CP, sa, c->stream));
+        }
+    }
+    for (int l = 0; l < c->N; ++l) {
+        auto &md = c->m[l];
+        HIPCHK(c, unpack_slab(c->prec, md.W, md.I, c->K, d_cur, ncols, c->ld, md.A, c->stream));
+    }
+    c->pend.assign(cols, cols + ncols);
+    return TF_OK;
+}
+
+tf_status reset_bad(tf_ctx *c)
+{
+    HIPCHK(c, hipMemsetAsync(c->d_bad, 0xff, kMaxModes * sizeof(unsigned long long), c->stream));
+    return TF_OK;
+}
+
+tf_status check_bad(tf_ctx *c)
+{
+    unsigned long long h[kMaxModes];
+    HIPCHK(c, hipMemcpyAsync(h, c->d_bad, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int n = 0; n < c->N; ++n)
+        if (h[n] != ULLONG_MAX)
+            return CTX_FAIL(c, TF_E_NUMERIC,
+                            "non-positive Cholesky pivot in mode %d row %llu (row kept its previous value)",
+                            n, (unsigned long long)h[n]);
+    return TF_OK;
+}
+
+tf_status check_ready(tf_ctx *c)
+{
+    if (c->stale) return CTX_FAIL(c, TF_E_STATE, "factors were set; call tf_resync first");
+    return TF_OK;
+}
+
+tf_status ensure_partials(tf_ctx *c, int64_t n)
+{
+    if (n <= c->partials_cap) return TF_OK;
+    dfree(c->d_partials);
+    c->d_partials = nullptr;
+    HIPCHK(c, dalloc(&c->d_partials, (size_t)n));
+    c->partials_cap = n;
+    return TF_OK;
+}
+
+// Sum of r^2 over all entries (and optionally r in input order).
+tf_status eval_residual(tf_ctx *c, double *d_rout, double *se_out)
+{
+    const int npend = (int)c->pend.size();
+    const int width = std::max(npend, 1);
+    c->ld = std::max<int64_t>(slab_ld(c, width), 1);
+    tf_status s;
+    if (npend > 0) {
+        if ((s = upload_cols(c, c->pend.data(), 0)) != TF_OK) return s;
+        if ((s = pack_all(c, c->d_cols + c->K, npend, width, true)) != TF_OK) return s;
+    }
+    auto &m0 = c->m[0];
+    EvalArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.rowptr = m0.rowptr;
+    a.tasks = m0.tasks;
+    a.ntasks = m0.ntasks;
+    a.items = m0.items;
+    a.chunks = m0.chunks;
+    for (int l = 1; l < c->N; ++l) {
+        a.oidx[l - 1] = m0.oidx[l - 1];
+        a.P[l - 1] = c->m[l].P;
+    }
+    a.rhat = m0.rhat;
+    a.Pown = m0.P;
+    a.npend = npend;
+    a.no = c->N - 1;
+    a.ld = c->ld;
+    a.perm = m0.perm;
+    a.r_out = d_rout;
+    const int grid = std::max(1, (m0.ntasks + 3) / 4);
+    if ((s = ensure_partials(c, grid)) != TF_OK) return s;
+    a.partials = c->d_partials;
+    HIPCHK(c, launch_eval_residual(c->prec, a, grid, c->stream));
+    HIPCHK(c, sum_partials(c->d_partials, grid, c->d_scalar, c->stream));
+    double h = 0.0;
+    HIPCHK(c, hipMemcpyAsync(&h, c->d_scalar, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *se_out = h;
+    return TF_OK;
+}
+
+void destroy_ctx(tf_ctx *c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    dfree(c->idx);
+    dfree(c->x);
+    for (int n = 0; n < kMaxModes; ++n) {
+        auto &md = c->m[n];
+        dfree(md.rowptr); dfree(md.perm);
+        for (int l = 0; l < kMaxModes - 1; ++l) dfree(md.oidx[l]);
+        dfree(md.rhat); dfree(md.A); dfree(md.W); dfree(md.S); dfree(md.P);
+        dfree(md.tasks); dfree(md.items); dfree(md.chunks);
+        dfree(md.split_rows); dfree(md.split_chunk_ptr);
+    }
+    dfree(c->gram); dfree(c->gpart); dfree(c->d_cols); dfree(c->d_bad);
+    dfree(c->d_partials); dfree(c->d_scalar);
+    for (auto e : c->ev_free) (void)hipEventDestroy(e);
+    for (auto &t : c->ev_pending) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
+    delete c;
+}
+
+template <typename T>
+tf_status upload_vec(tf_ctx *c, T **dst, const std::vector<T> &v)
+{
+    HIPCHK(c, dalloc(dst, v.size()));
+    if (!v.empty())
+        HIPCHK(c, hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return TF_OK;
+}
+
+tf_status build_state(tf_ctx *c, const int32_t *d_idx, const double *d_vals)
+{
+    const int N = c->N;
+    const int64_t nnz = c->nnz;
+    hipStream_t st = c->stream;
+    HIPCHK(c, dalloc(&c->idx, (size_t)nnz * N));
+    HIPCHK(c, dalloc(&c->x, (size_t)nnz));
+    HIPCHK(c, hipMemcpyAsync(c->idx, d_idx, (size_t)nnz * N * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(c->x, d_vals, (size_t)nnz * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHK(c, dalloc(&c->d_bad, kMaxModes));
+    HIPCHK(c, dalloc(&c->d_scalar, 4));
+    HIPCHK(c, dalloc(&c->d_cols, 2 * (size_t)c->K + 2));
+
+    // validation: first bad index tuple and first non-finite value
+    HIPCHK(c, hipMemsetAsync(c->d_bad, 0xff, 2 * sizeof(unsigned long long), st));
+    HIPCHK(c, validate_input(c->idx, c->x, nnz, N, c->dims, c->d_bad, c->d_bad + 1, st));
+    unsigned long long hb[2];
+    HIPCHK(c, hipMemcpyAsync(hb, c->d_bad, sizeof hb, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (hb[0] != ULLONG_MAX)
+        return CTX_FAIL(c, TF_E_INVALID, "entry %llu has an index outside its mode length", hb[0]);
+    if (hb[1] != ULLONG_MAX)
+        return CTX_FAIL(c, TF_E_INVALID, "entry %llu has a non-finite value", hb[1]);
+
+    // CSR per mode (stable sort of entry ids by row)
+    int32_t *k0 = nullptr, *k1 = nullptr, *v1 = nullptr, *hist = nullptr, *stmp = nullptr;
+    const int64_t hcap = sort_hist_size(nnz);
+    const int64_t scap = scan_tmp_size(hcap);
+    struct Tmp { int32_t **p; ~Tmp() { for (int i = 0; i < 5; ++i) dfree(p[i]); } };
+    int32_t *tmps[5] = {nullptr};
+    Tmp guard{tmps};
+    HIPCHK(c, dalloc(&k0, (size_t)nnz)); tmps[0] = k0;
+    HIPCHK(c, dalloc(&k1, (size_t)nnz)); tmps[1] = k1;
+    HIPCHK(c, dalloc(&v1, (size_t)nnz)); tmps[2] = v1;
+    HIPCHK(c, dalloc(&hist, (size_t)hcap)); tmps[3] = hist;
+    HIPCHK(c, dalloc(&stmp, (size_t)scap)); tmps[4] = stmp;
+
+    for (int n = 0; n < N; ++n) {
+        auto &md = c->m[n];
+        md.I = c->dims[n];
+        HIPCHK(c, dalloc(&md.perm, (size_t)nnz));
+        HIPCHK(c, dalloc(&md.rowptr, (size_t)md.I + 1));
+        HIPCHK(c, stable_sort_by_key(c->idx, N, n, nnz, key_bits_for(md.I), md.perm, k0, k1, v1,
+                                     hist, hcap, stmp, scap, st));
+        HIPCHK(c, rowptr_from_sorted(k0, nnz, md.I, md.rowptr, st));
+        int t = 0;
+        for (int l = 0; l < N; ++l) {
+            if (l == n) continue;
+            HIPCHK(c, dalloc(&md.oidx[t], (size_t)nnz));
+            HIPCHK(c, gather_other_index(c->idx, N, l, md.perm, nnz, md.oidx[t], st));
+            ++t;
+        }
+        std::vector<int32_t> rp32((size_t)md.I + 1);
+        HIPCHK(c, hipMemcpyAsync(rp32.data(), md.rowptr, rp32.size() * sizeof(int32_t),
+                                 hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        md.h_rowptr.assign(rp32.begin(), rp32.end());
+        HostPlan plan;
+        plan_rows(md.h_rowptr.data(), md.I, c->opt.strategy, c->opt.lane_nnz,
+                  c->opt.split_threshold, c->opt.chunk_nnz, &plan);
+        tf_status s;
+        if ((s = upload_vec(c, &md.tasks, plan.tasks)) != TF_OK) return s;
+        if ((s = upload_vec(c, &md.items, plan.items)) != TF_OK) return s;
+        if ((s = upload_vec(c, &md.chunks, plan.chunks)) != TF_OK) return s;
+        if ((s = upload_vec(c, &md.split_rows, plan.split_rows)) != TF_OK) return s;
+        if ((s = upload_vec(c, &md.split_chunk_ptr, plan.split_chunk_ptr)) != TF_OK) return s;
+        md.ntasks = (int32_t)plan.tasks.size();
+        md.nchunks = (int32_t)plan.chunks.size();
+        md.nsplit = (int32_t)plan.split_rows.size();
+    }
+
+    // factors (Section 3.1: A^(1) = 0, the others random, so that R = X)
+    const size_t sf = ts_size(c->prec);
+    uint64_t offset = 0;
+    for (int n = 0; n < N; ++n) {
+        auto &md = c->m[n];
+        HIPCHK(c, hipMalloc(&md.A, (size_t)md.I * c->K * sf));
+        const bool zero = c->opt.first_factor_zero && n == 0;
+        HIPCHK(c, init_factor(c->prec, md.A, md.I, c->K, c->opt.seed, offset, zero, st));
+        offset += (uint64_t)md.I * (uint64_t)c->K;
+        const size_t slab = (size_t)md.I * (size_t)slab_cap_elems(c) * sf;
+        HIPCHK(c, hipMalloc(&md.W, slab));
+        HIPCHK(c, hipMalloc(&md.S, slab));
+        HIPCHK(c, hipMalloc(&md.P, slab));
+        HIPCHK(c, hipMemsetAsync(md.W, 0, slab, st));
+        HIPCHK(c, hipMemsetAsync(md.S, 0, slab, st));
+        HIPCHK(c, hipMemsetAsync(md.P, 0, slab, st));
+        HIPCHK(c, hipMalloc(&md.rhat, (size_t)nnz * tr_size(c->prec)));
+    }
+    // residual r = x - reconstruction (exactly x when A^(1) = 0)
+    double *r = nullptr;
+    HIPCHK(c, dalloc(&r, (size_t)nnz));
+    const void *A[kMaxModes];
+    for (int n = 0; n < N; ++n) A[n] = c->m[n].A;
+    hipError_t e = residual_input_order(c->prec, c->idx, c->x, nnz, N, A, c->K,
+                                        c->opt.first_factor_zero != 0, r, st);
+    for (int n = 0; n < N && e == hipSuccess; ++n)
+        e = gather_residual(c->prec, r, c->m[n].perm, nnz, c->m[n].rhat, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    dfree(r);
+    if (e != hipSuccess) return CTX_FAIL(c, TF_E_DEVICE, "residual: %s", hipGetErrorString(e));
+    c->order.resize(c->K);
+    for (int k = 0; k < c->K; ++k) c->order[k] = k;
+    c->pend.clear();
+    return TF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void tf_default_options(tf_options *opt)
+{
+    if (!opt) return;
+    std::memset(opt, 0, sizeof *opt);
+    opt->size = sizeof(tf_options);
+    opt->precision = TF_PREC_F32;
+    opt->reg_mode = 0;
+    opt->first_factor_zero = 1;
+    opt->strategy = TF_STRATEGY_SKEW;
+    opt->seed = 2;
+    opt->stream = nullptr;
+    opt->lane_nnz = 8;
+    opt->split_threshold = 4096;
+    opt->chunk_nnz = 2048;
+    opt->slab_pad = 16;
+}
+
+const char *tf_last_error(const tf_ctx *ctx)
+{
+    return ctx ? ctx->err.c_str() : g_init_err.c_str();
+}
+
+tf_status tf_init(tf_ctx **out, int32_t N, const int64_t *dims, int64_t nnz, const int32_t *d_idx,
+                  const double *d_vals, int32_t K, double lambda, const tf_options *opt)
+{
+    g_init_err.clear();
+    if (!out) return set_err(&g_init_err, TF_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (N < 2 || N > kMaxModes) return set_err(&g_init_err, TF_E_INVALID, "N = %d outside [2, 8]", N);
+    if (!dims || !d_idx || !d_vals) return set_err(&g_init_err, TF_E_INVALID, "NULL pointer argument");
+    for (int n = 0; n < N; ++n)
+        if (dims[n] < 1 || dims[n] > INT32_MAX)
+            return set_err(&g_init_err, TF_E_INVALID, "dims[%d] = %lld outside [1, 2^31-1]", n, (long long)dims[n]);
+    if (nnz < 1 || nnz > INT32_MAX)
+        return set_err(&g_init_err, TF_E_INVALID, "nnz = %lld outside [1, 2^31-1]", (long long)nnz);
+    if (K < 1) return set_err(&g_init_err, TF_E_INVALID, "K = %d < 1", K);
+    if (!(lambda > 0.0) || !std::isfinite(lambda))
+        return set_err(&g_init_err, TF_E_INVALID, "lambda must be positive and finite");
+    tf_options o;
+    tf_default_options(&o);
+    if (opt) {
+        if (opt->size != sizeof(tf_options))
+            return set_err(&g_init_err, TF_E_INVALID, "tf_options.size mismatch");
+        o = *opt;
+    }
+    if (o.precision < 0 || o.precision > 2) return set_err(&g_init_err, TF_E_INVALID, "bad precision");
+    if (o.reg_mode != 0 && o.reg_mode != 1) return set_err(&g_init_err, TF_E_INVALID, "bad reg_mode");
+    if (o.strategy != TF_STRATEGY_PLAIN && o.strategy != TF_STRATEGY_SKEW)
+        return set_err(&g_init_err, TF_E_INVALID, "bad strategy");
+    if (o.lane_nnz < 0 || o.split_threshold < 0 || o.chunk_nnz < 0)
+        return set_err(&g_init_err, TF_E_INVALID, "negative tuning option");
+    if (o.slab_pad == 0) o.slab_pad = 16;
+    if (o.slab_pad != 16 && o.slab_pad != 64) return set_err(&g_init_err, TF_E_INVALID, "slab_pad must be 16 or 64");
+    if (o.lane_nnz == 0) o.lane_nnz = 8;
+    if (o.split_threshold == 0) o.split_threshold = 4096;
+    if (o.chunk_nnz == 0) o.chunk_nnz = 2048;
+
+    int dev = 0;
+    hipError_t he = hipGetDevice(&dev);
+    if (he != hipSuccess) return set_err(&g_init_err, TF_E_DEVICE, "no HIP device: %s", hipGetErrorString(he));
+
+    tf_ctx *c = new (std::nothrow) tf_ctx();
+    if (!c) return set_err(&g_init_err, TF_E_NOMEM, "host allocation failed");
+    c->N = N;
+    c->nnz = nnz;
+    c->K = K;
+    c->lambda = lambda;
+    c->opt = o;
+    c->prec = o.precision;
+    c->stream = (hipStream_t)o.stream;
+    c->device = dev;
+    for (int n = 0; n < N; ++n) c->dims[n] = dims[n];
+    tf_status s = build_state(c, d_idx, d_vals);
+    if (s != TF_OK) {
+        g_init_err = c->err;
+        destroy_ctx(c);
+        return s;
+    }
+    *out = c;
+    return TF_OK;
+}
+
+void tf_destroy(tf_ctx *ctx) { destroy_ctx(ctx); }
+
+tf_status tf_split(tf_ctx *ctx, int32_t ncols, const int32_t *h_cols, int32_t T_in)
+{
+    if (!ctx) return TF_E_INVALID;
+    if (!h_cols || ncols < 1 || ncols > ctx->K || T_in < 1)
+        return CTX_FAIL(ctx, TF_E_INVALID, "need 1 <= ncols <= K, T_in >= 1");
+    for (int q = 0; q < ncols; ++q) {
+        if (h_cols[q] < 0 || h_cols[q] >= ctx->K) return CTX_FAIL(ctx, TF_E_INVALID, "column %d out of range", h_cols[q]);
+        for (int p = 0; p < q; ++p)
+            if (h_cols[p] == h_cols[q]) return CTX_FAIL(ctx, TF_E_INVALID, "column %d repeated", h_cols[q]);
+    }
+    if (ncols > kMaxC) return CTX_FAIL(ctx, TF_E_UNSUPPORTED, "C = %d exceeds %d", ncols, kMaxC);
+    tf_status s = check_ready(ctx);
+    if (s != TF_OK) return s;
+    if ((s = reset_bad(ctx)) != TF_OK) return s;
+    if ((s = run_split(ctx, h_cols, ncols, T_in)) != TF_OK) return s;
+    return check_bad(ctx);
+}
+
+tf_status tf_sweep(tf_ctx *ctx, int32_t C, int32_t T_in)
+{
+    if (!ctx) return TF_E_INVALID;
+    if (C < 1 || C > ctx->K || T_in < 1) return CTX_FAIL(ctx, TF_E_INVALID, "need 1 <= C <= K, T_in >= 1");
+    if (C > kMaxC) return CTX_FAIL(ctx, TF_E_UNSUPPORTED, "C = %d exceeds %d", C, kMaxC);
+    tf_status s = check_ready(ctx);
+    if (s != TF_OK) return s;
+    if ((s = reset_bad(ctx)) != TF_OK) return s;
+    for (int b = 0; b < ctx->K; b += C) {
+        const int w = std::min(C, ctx->K - b);
+        if ((s = run_split(ctx, ctx->order.data() + b, w, T_in)) != TF_OK) return s;
+    }
+    ctx->kstats.sweeps += 1;
+    return check_bad(ctx);
+}
+
+tf_status tf_set_col_order(tf_ctx *ctx, const int32_t *h_order)
+{
+    if (!ctx) return TF_E_INVALID;
+    if (!h_order) return CTX_FAIL(ctx, TF_E_INVALID, "NULL order");
+    std::vector<char> seen(ctx->K, 0);
+    for (int k = 0; k < ctx->K; ++k) {
+        if (h_order[k] < 0 || h_order[k] >= ctx->K || seen[h_order[k]])
+            return CTX_FAIL(ctx, TF_E_INVALID, "order is not a permutation of 0..K-1");
+        seen[h_order[k]] = 1;
+    }
+    ctx->order.assign(h_order, h_order + ctx->K);
+    return TF_OK;
+}
+
+tf_status tf_get_col_order(const tf_ctx *ctx, int32_t *h_order)
+{
+    if (!ctx || !h_order) return TF_E_INVALID;
+    std::memcpy(h_order, ctx->order.data(), ctx->K * sizeof(int32_t));
+    return TF_OK;
+}
+
+tf_status tf_loss(tf_ctx *ctx, double *loss, double *train_rmse)
+{
+    if (!ctx) return TF_E_INVALID;
+    tf_status s = check_ready(ctx);
+    if (s != TF_OK) return s;
+    double se = 0.0;
+    if ((s = eval_residual(ctx, nullptr, &se)) != TF_OK) return s;
+    int64_t nb_total = 0;
+    int nb[kMaxModes];
+    for (int n = 0; n < ctx->N; ++n) {
+        nb[n] = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (ctx->m[n].I + 255) / 256));
+        nb_total += nb[n];
+    }
+    if ((s = ensure_partials(ctx, nb_total)) != TF_OK) return s;
+    int64_t off = 0;
+    for (int n = 0; n < ctx->N; ++n) {
+        HIPCHK(ctx, reg_partials(ctx->prec, ctx->m[n].A, ctx->m[n].I, ctx->K, ctx->m[n].rowptr,
+                                 ctx->opt.reg_mode, ctx->d_partials + off, nb[n], ctx->stream));
+        off += nb[n];
+    }
+    HIPCHK(ctx, sum_partials(ctx->d_partials, nb_total, ctx->d_scalar + 1, ctx->stream));
+    double reg = 0.0;
+    HIPCHK(ctx, hipMemcpyAsync(&reg, ctx->d_scalar + 1, sizeof reg, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (loss) *loss = se + ctx->lambda * reg;
+    if (train_rmse) *train_rmse = std::sqrt(se / (double)ctx->nnz);
+    if (!std::isfinite(se) || !std::isfinite(reg))
+        return CTX_FAIL(ctx, TF_E_NUMERIC, "loss is not finite");
+    return TF_OK;
+}
+
+tf_status tf_get_residual(tf_ctx *ctx, double *h)
+{
+    if (!ctx) return TF_E_INVALID;
+    if (!h) return CTX_FAIL(ctx, TF_E_INVALID, "NULL output");
+    tf_status s = check_ready(ctx);
+    if (s != TF_OK) return s;
+    double *d = nullptr;
+    HIPCHK(ctx, dalloc(&d, (size_t)ctx->nnz));
+    double se = 0.0;
+    s = eval_residual(ctx, d, &se);
+    if (s == TF_OK) {
+        hipError_t e = hipMemcpy(h, d, (size_t)ctx->nnz * sizeof(double), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) s = CTX_FAIL(ctx, TF_E_DEVICE, "copy: %s", hipGetErrorString(e));
+    }
+    dfree(d);
+    return s;
+}
+
+tf_status tf_resync(tf_ctx *ctx)
+{
+    if (!ctx) return TF_E_INVALID;
+    double *r = nullptr;
+    HIPCHK(ctx, dalloc(&r, (size_t)ctx->nnz));
+    const void *A[kMaxModes];
+    for (int n = 0; n < ctx->N; ++n) A[n] = ctx->m[n].A;
+    hipError_t e = residual_input_order(ctx->prec, ctx->idx, ctx->x, ctx->nnz, ctx->N, A, ctx->K,
+                                        false, r, ctx->stream);
+    for (int n = 0; n < ctx->N && e == hipSuccess; ++n)
+        e = gather_residual(ctx->prec, r, ctx->m[n].perm, ctx->nnz, ctx->m[n].rhat, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    dfree(r);
+    if (e != hipSuccess) return CTX_FAIL(ctx, TF_E_DEVICE, "resync: %s", hipGetErrorString(e));
+    ctx->pend.clear();
+    ctx->stale = false;
+    return TF_OK;
+}
+
+tf_status tf_get_factor(tf_ctx *ctx, int32_t n, double *h)
+{
+    if (!ctx) return TF_E_INVALID;
+    if (n < 0 || n >= ctx->N || !h) return CTX_FAIL(ctx, TF_E_INVALID, "bad mode or NULL output");
+    const int64_t cnt = ctx->m[n].I * ctx->K;
+    double *d = nullptr;
+    HIPCHK(ctx, dalloc(&d, (size_t)cnt));
+    hipError_t e = factor_to_f64(ctx->prec, ctx->m[n].A, cnt, d, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess) e = hipMemcpy(h, d, (size_t)cnt * sizeof(double), hipMemcpyDeviceToHost);
+    dfree(d);
+    if (e != hipSuccess) return CTX_FAIL(ctx, TF_E_DEVICE, "get_factor: %s", hipGetErrorString(e));
+    return TF_OK;
+}
+
+tf_status tf_set_factor(tf_ctx *ctx, int32_t n, const double *h)
+{
+    if (!ctx) return TF_E_INVALID;
+    if (n < 0 || n >= ctx->N || !h) return CTX_FAIL(ctx, TF_E_INVALID, "bad mode or NULL input");
+    const int64_t cnt = ctx->m[n].I * ctx->K;
+    for (int64_t t = 0; t < cnt; ++t)
+        if (!std::isfinite(h[t])) return CTX_FAIL(ctx, TF_E_INVALID, "factor entry %lld is not finite", (long long)t);
+    double *d = nullptr;
+    HIPCHK(ctx, dalloc(&d, (size_t)cnt));
+    hipError_t e = hipMemcpy(d, h, (size_t)cnt * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = factor_from_f64(ctx->prec, d, cnt, ctx->m[n].A, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    dfree(d);
+    if (e != hipSuccess) return CTX_FAIL(ctx, TF_E_DEVICE, "set_factor: %s", hipGetErrorString(e));
+    ctx->stale = true;
+    return TF_OK;
+}
+
+tf_status tf_get_csr(tf_ctx *ctx, int32_t n, int64_t *h_rowptr, int32_t *h_perm)
+{
+    if (!ctx) return TF_E_INVALID;
+    if (n < 0 || n >= ctx->N || !h_rowptr || !h_perm) return CTX_FAIL(ctx, TF_E_INVALID, "bad arguments");
+    std::vector<int32_t> rp((size_t)ctx->m[n].I + 1);
+    HIPCHK(ctx, hipMemcpy(rp.data(), ctx->m[n].rowptr, rp.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < rp.size(); ++i) h_rowptr[i] = rp[i];
+    HIPCHK(ctx, hipMemcpy(h_perm, ctx->m[n].perm, (size_t)ctx->nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+    return TF_OK;
+}
+
+tf_status tf_predict(tf_ctx *ctx, int64_t m, const int32_t *d_idx, double *d_out)
+{
+    if (!ctx) return TF_E_INVALID;
+    if (m < 0) return CTX_FAIL(ctx, TF_E_INVALID, "m < 0");
+    if (m == 0) return TF_OK;
+    if (!d_idx || !d_out) return CTX_FAIL(ctx, TF_E_INVALID, "NULL pointer argument");
+    const void *A[kMaxModes];
+    for (int n = 0; n < ctx->N; ++n) A[n] = ctx->m[n].A;
+    HIPCHK(ctx, hipMemsetAsync(ctx->d_bad, 0xff, sizeof(unsigned long long), ctx->stream));
+    HIPCHK(ctx, launch_predict(ctx->prec, ctx->N, ctx->K, A, ctx->dims, d_idx, m, d_out, ctx->d_bad, ctx->stream));
+    unsigned long long hb = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&hb, ctx->d_bad, sizeof hb, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (hb != ULLONG_MAX) return CTX_FAIL(ctx, TF_E_INVALID, "query %llu has an index out of range", hb);
+    return TF_OK;
+}
+
+tf_status tf_profile(tf_ctx *ctx, int32_t enable)
+{
+    if (!ctx) return TF_E_INVALID;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto &t : ctx->ev_pending) { ctx->ev_free.push_back(t.a); ctx->ev_free.push_back(t.b); }
+    ctx->ev_pending.clear();
+    ctx->kstats = tf_kstats{};
+    ctx->profiling = enable != 0;
+    return TF_OK;
+}
+
+tf_status tf_profile_read(tf_ctx *ctx, tf_kstats *out)
+{
+    if (!ctx || !out) return TF_E_INVALID;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (auto &t : ctx->ev_pending) {
+        float ms = 0.f;
+        HIPCHK(ctx, hipEventElapsedTime(&ms, t.a, t.b));
+        ctx->kstats.launches += 1;
+        ctx->kstats.total_ms += ms;
+        ctx->kstats.alg_bytes += t.bytes;
+        ctx->ev_free.push_back(t.a);
+        ctx->ev_free.push_back(t.b);
+    }
+    ctx->ev_pending.clear();
+    *out = ctx->kstats;
+    return TF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,223 @@
+// Internal declarations of the SALS / CDTF GPU library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tf.h"
+
+namespace tfk {
+
+// ---------------------------------------------------------------- precision
+enum Prec { P_F64 = 0, P_F32 = 1, P_BF16 = 2 };
+
+struct bf16 {
+    uint16_t bits;
+};
+
+// Largest number of columns per split the register kernels are built for.
+constexpr int kMaxC = 16;
+constexpr int kMaxModes = 8;
+
+// Gram record of one row: upper triangle of B (c1 <= c2, row-major) then the
+// right-hand side c; padded to a multiple of 4 entries.
+__host__ __device__ constexpr int gram_entries(int CP) { return CP * (CP + 1) / 2 + CP; }
+__host__ __device__ constexpr int gram_stride(int CP) { return (gram_entries(CP) + 3) & ~3; }
+
+// Compute widths the row kernels are instantiated for; C is padded up to the
+// next one (padded slab columns hold zeros, which leaves the solution of the
+// real columns unchanged and the padded ones at zero).
+int pick_cp(int C, int prec);
+
+// ---------------------------------------------------------------- work plan
+// A task is one wavefront's unit of work.
+//   kind 0: up to 64/G rows, G lanes each (items[base .. base+count))
+//   kind 1: one chunk of a long row (chunks[base]), 64 lanes
+struct Task {
+    int32_t G;
+    int32_t base;
+    int32_t count;
+    int32_t kind;
+};
+struct Chunk {
+    int32_t row;
+    int32_t beg;
+    int32_t end;
+    int32_t slot;
+};
+
+struct HostPlan {
+    std::vector<Task> tasks;
+    std::vector<int32_t> items;
+    std::vector<Chunk> chunks;
+    std::vector<int32_t> split_rows;     // rows cut into chunks
+    std::vector<int32_t> split_chunk_ptr;// chunk range per split row (size+1)
+    int64_t empty_rows = 0;
+    int64_t rows_by_lanes[7] = {0, 0, 0, 0, 0, 0, 0};
+};
+
+void plan_rows(const int64_t *rowptr, int64_t I, int strategy, int lane_nnz, int split_threshold,
+               int chunk_nnz, HostPlan *out);
+
+// ---------------------------------------------------------------- kernel args
+struct AccumArgs {
+    const int32_t *rowptr;
+    const Task *tasks;
+    int32_t ntasks;
+    const int32_t *items;
+    const Chunk *chunks;
+    const int32_t *oidx[kMaxModes - 1];  // other modes ascending, CSR order
+    void *rhat;                          // residual copy of this mode (CSR order)
+    const void *W[kMaxModes - 1];        // other modes: current slabs
+    const void *S[kMaxModes - 1];        // other modes: split-start slabs
+    const void *P[kMaxModes - 1];        // other modes: pending-column slabs
+    int32_t before[kMaxModes - 1];       // 1: that mode was updated earlier in this split
+    const void *Sown;                    // this mode: split-start slab
+    const void *Pown;                    // this mode: pending-column slab
+    int32_t has_pend;
+    int32_t no;                          // number of other modes (N - 1)
+    int64_t ld;                          // slab row stride (elements)
+    void *gram;                          // per-row Gram records
+    void *gpart;                         // per-chunk partial Gram records
+};
+
+struct SolveArgs {
+    const int32_t *rowptr;
+    int64_t I;
+    const void *gram;
+    void *W;            // slab of the mode being updated
+    int64_t ld;
+    double lambda;
+    int32_t reg_mode;
+    unsigned long long *bad;   // smallest failing row (init ULLONG_MAX)
+};
+
+// launchers (return hipError_t of the launch)
+hipError_t launch_accum(int prec, int CP, int no, bool first, const AccumArgs &a, int grid,
+                        hipStream_t st);
+hipError_t launch_solve(int prec, int CP, const SolveArgs &a, hipStream_t st);
+hipError_t launch_chunk_reduce(int prec, int CP, const int32_t *split_rows,
+                               const int32_t *split_chunk_ptr, int nsplit, const void *gpart,
+                               void *gram, hipStream_t st);
+
+// ---------------------------------------------------------------- build kernels
+hipError_t validate_input(const int32_t *idx, const double *vals, int64_t nnz, int N,
+                          const int64_t *dims, unsigned long long *bad_idx,
+                          unsigned long long *bad_val, hipStream_t st);
+// stable sort of entry ids by key (keys < 2^bits); tmp buffers of nnz each
+hipError_t stable_sort_by_key(const int32_t *idx, int N, int mode, int64_t nnz, int key_bits,
+                              int32_t *perm_out, int32_t *k0, int32_t *k1, int32_t *v1,
+                              int32_t *hist, int64_t hist_cap, int32_t *scan_tmp,
+                              int64_t scan_tmp_cap, hipStream_t st);
+int64_t sort_hist_size(int64_t nnz);
+int64_t scan_tmp_size(int64_t n);
+hipError_t rowptr_from_sorted(const int32_t *sorted_keys, int64_t nnz, int64_t I, int32_t *rowptr,
+                              hipStream_t st);
+hipError_t gather_other_index(const int32_t *idx, int N, int l, const int32_t *perm, int64_t nnz,
+                              int32_t *out, hipStream_t st);
+hipError_t init_factor(int prec, void *A, int64_t I, int K, uint64_t seed, uint64_t offset,
+                       bool zero, hipStream_t st);
+hipError_t residual_input_order(int prec, const int32_t *idx, const double *x, int64_t nnz,
+                                int N, const void *const *A, int K, bool zero_model,
+                                double *r_out, hipStream_t st);
+hipError_t gather_residual(int prec, const double *r_in, const int32_t *perm, int64_t nnz,
+                           void *rhat_out, hipStream_t st);
+hipError_t factor_to_f64(int prec, const void *A, int64_t n, double *out, hipStream_t st);
+hipError_t factor_from_f64(int prec, const double *in, int64_t n, void *A, hipStream_t st);
+
+// ---------------------------------------------------------------- slabs
+hipError_t pack_slab(int prec, const void *A, int64_t I, int K, const int32_t *cols, int ncols,
+                     int CP, int64_t ld, void *out1, void *out2, hipStream_t st);
+hipError_t unpack_slab(int prec, const void *W, int64_t I, int K, const int32_t *cols, int ncols,
+                       int64_t ld, void *A, hipStream_t st);
+
+// ---------------------------------------------------------------- evaluation
+struct EvalArgs {
+    const int32_t *rowptr;   // mode 0
+    const Task *tasks;
+    int32_t ntasks;
+    const int32_t *items;
+    const Chunk *chunks;
+    const int32_t *oidx[kMaxModes - 1];
+    const void *rhat;        // mode-0 copy
+    const void *P[kMaxModes - 1];  // pending-column slabs of the other modes
+    const void *Pown;              // pending-column slab of mode 0
+    int32_t npend;
+    int32_t no;
+    int64_t ld;
+    const int32_t *perm;     // mode-0 CSR perm (for scatter to input order)
+    double *r_out;           // if non-null: residual in input order
+    double *partials;        // per-block sum of r^2
+};
+hipError_t launch_eval_residual(int prec, const EvalArgs &a, int grid, hipStream_t st);
+hipError_t sync_copy(int prec, const AccumArgs &a, int npend, int ncur, int grid,
+                     hipStream_t st);
+hipError_t reg_partials(int prec, const void *A, int64_t I, int K, const int32_t *rowptr,
+                        int weighted, double *partials, int nblocks, hipStream_t st);
+hipError_t sum_partials(const double *partials, int64_t n, double *out, hipStream_t st);
+hipError_t launch_predict(int prec, int N, int K, const void *const *A, const int64_t *dims,
+                          const int32_t *q, int64_t m, double *out,
+                          unsigned long long *bad, hipStream_t st);
+
+}  // namespace tfk
+
+// ---------------------------------------------------------------- context
+struct tf_ctx {
+    int N = 0;
+    int64_t dims[tfk::kMaxModes] = {0};
+    int64_t nnz = 0;
+    int K = 0;
+    double lambda = 0.0;
+    tf_options opt{};
+    int prec = 1;
+    hipStream_t stream = nullptr;
+    int device = 0;
+
+    int32_t *idx = nullptr;   // nnz x N, input order
+    double *x = nullptr;      // nnz, input order
+
+    struct Mode {
+        int64_t I = 0;
+        int32_t *rowptr = nullptr;     // I + 1
+        int32_t *perm = nullptr;       // nnz
+        int32_t *oidx[tfk::kMaxModes - 1] = {nullptr};
+        void *rhat = nullptr;          // nnz (TR)
+        void *A = nullptr;             // I x K (TS)
+        void *W = nullptr, *S = nullptr, *P = nullptr;  // slabs I x ld (TS)
+        tfk::Task *tasks = nullptr;
+        int32_t ntasks = 0;
+        int32_t *items = nullptr;
+        tfk::Chunk *chunks = nullptr;
+        int32_t nchunks = 0;
+        int32_t *split_rows = nullptr;
+        int32_t *split_chunk_ptr = nullptr;
+        int32_t nsplit = 0;
+        std::vector<int64_t> h_rowptr;
+    } m[tfk::kMaxModes];
+
+    int64_t ld = 0;           // slab row stride (elements)
+    int slab_cp = 0;          // compute width the slabs are sized for
+    void *gram = nullptr;     // max_I x gram_stride(slab_cp) (TA)
+    void *gpart = nullptr;    // max_chunks x gram_stride(slab_cp) (TA)
+    int32_t *d_cols = nullptr;  // device copy of split columns + pending columns
+    unsigned long long *d_bad = nullptr;  // [0] failing row, [1] scratch
+    double *d_partials = nullptr;
+    int64_t partials_cap = 0;
+    double *d_scalar = nullptr;
+
+    std::vector<int32_t> order;     // column order for sweeps
+    std::vector<int32_t> pend;      // columns whose contribution is pending in the copies
+    bool stale = false;             // factors set without resync
+    bool dirty = false;             // a numeric failure left the state inconsistent
+
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_free;
+    struct Timed { hipEvent_t a, b; double bytes; };
+    std::vector<Timed> ev_pending;
+    tf_kstats kstats{};
+
+    std::string err;
+};

@@ -1,0 +1,219 @@
+"""Thin ctypes binding of the C ABI in include/tf.h (argument marshalling only).
+
+Every function has the name of the C entry point it calls.  Device buffers are
+passed as torch tensors (their data pointers); host buffers as numpy arrays.
+All computation runs in the HIP library; if it is missing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtfsals.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "tf.h")
+
+TF_OK, TF_E_INVALID, TF_E_NOMEM, TF_E_DEVICE, TF_E_NUMERIC, TF_E_UNSUPPORTED, TF_E_BUSY, TF_E_STATE = range(8)
+TF_PREC_F64, TF_PREC_F32, TF_PREC_BF16 = 0, 1, 2
+TF_STRATEGY_PLAIN, TF_STRATEGY_SKEW = 0, 1
+PREC = {"f64": TF_PREC_F64, "f32": TF_PREC_F32, "bf16": TF_PREC_BF16}
+
+
+class tf_options(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint32), ("precision", ctypes.c_int32),
+                ("reg_mode", ctypes.c_int32), ("first_factor_zero", ctypes.c_int32),
+                ("strategy", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("stream", ctypes.c_void_p), ("lane_nnz", ctypes.c_int32),
+                ("split_threshold", ctypes.c_int32), ("chunk_nnz", ctypes.c_int32),
+                ("slab_pad", ctypes.c_int32)]
+
+
+class tf_kstats(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("alg_bytes", ctypes.c_double), ("sweeps", ctypes.c_int64)]
+
+
+class tf_plan_summary(ctypes.Structure):
+    _fields_ = [("tasks", ctypes.c_int64), ("split_rows", ctypes.c_int64),
+                ("chunks", ctypes.c_int64), ("empty_rows", ctypes.c_int64),
+                ("rows_by_lanes", ctypes.c_int64 * 7)]
+
+
+class TFError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"tf status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libtfsals.so (built by paper_1410_5209_amd.build); raises if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.tf_default_options.argtypes = [ctypes.POINTER(tf_options)]
+        L.tf_default_options.restype = None
+        L.tf_init.argtypes = [ctypes.POINTER(P), i32, P, i64, P, P, i32, f64, ctypes.POINTER(tf_options)]
+        L.tf_destroy.argtypes = [P]
+        L.tf_destroy.restype = None
+        L.tf_last_error.argtypes = [P]
+        L.tf_last_error.restype = ctypes.c_char_p
+        L.tf_sweep.argtypes = [P, i32, i32]
+        L.tf_split.argtypes = [P, i32, P, i32]
+        L.tf_set_col_order.argtypes = [P, P]
+        L.tf_get_col_order.argtypes = [P, P]
+        L.tf_loss.argtypes = [P, ctypes.POINTER(f64), ctypes.POINTER(f64)]
+        L.tf_predict.argtypes = [P, i64, P, P]
+        L.tf_get_factor.argtypes = [P, i32, P]
+        L.tf_set_factor.argtypes = [P, i32, P]
+        L.tf_resync.argtypes = [P]
+        L.tf_get_residual.argtypes = [P, P]
+        L.tf_get_csr.argtypes = [P, i32, P, P]
+        L.tf_profile.argtypes = [P, i32]
+        L.tf_profile_read.argtypes = [P, ctypes.POINTER(tf_kstats)]
+        L.tf_plan_rows.argtypes = [P, i64, i32, i32, i32, i32, ctypes.POINTER(tf_plan_summary)]
+        for name in ("tf_init", "tf_sweep", "tf_split", "tf_set_col_order", "tf_get_col_order",
+                     "tf_loss", "tf_predict", "tf_get_factor", "tf_set_factor", "tf_resync",
+                     "tf_get_residual", "tf_get_csr", "tf_profile", "tf_profile_read",
+                     "tf_plan_rows"):
+            getattr(L, name).restype = ctypes.c_int32
+        _lib = L
+    return _lib
+
+
+def _np(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _dev(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check(ctx, status):
+    if status != TF_OK:
+        raise TFError(status, lib().tf_last_error(ctx).decode())
+
+
+def tf_default_options(**kw) -> tf_options:
+    o = tf_options()
+    lib().tf_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = PREC[v]
+        if k == "stream" and v is not None and not isinstance(v, int):
+            v = v.cuda_stream  # a torch.cuda.Stream
+        setattr(o, k, v)
+    return o
+
+
+def tf_init(dims, d_idx, d_vals, K, lam, opt: tf_options | None = None):
+    """d_idx: device int32 (nnz, N); d_vals: device float64 (nnz,). Returns ctx."""
+    dims_a = np.ascontiguousarray(dims, dtype=np.int64)
+    assert d_idx.is_contiguous() and d_vals.is_contiguous()
+    ctx = ctypes.c_void_p()
+    st = lib().tf_init(ctypes.byref(ctx), len(dims_a), _np(dims_a), int(d_vals.shape[0]),
+                       _dev(d_idx), _dev(d_vals), int(K), float(lam),
+                       ctypes.byref(opt) if opt is not None else None)
+    _check(None, st)
+    return ctx
+
+
+def tf_destroy(ctx):
+    lib().tf_destroy(ctx)
+
+
+def tf_last_error(ctx):
+    return lib().tf_last_error(ctx).decode()
+
+
+def tf_sweep(ctx, C, T_in=1):
+    _check(ctx, lib().tf_sweep(ctx, int(C), int(T_in)))
+
+
+def tf_split(ctx, cols, T_in=1):
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    _check(ctx, lib().tf_split(ctx, int(cols.shape[0]), _np(cols), int(T_in)))
+
+
+def tf_set_col_order(ctx, order):
+    order = np.ascontiguousarray(order, dtype=np.int32)
+    _check(ctx, lib().tf_set_col_order(ctx, _np(order)))
+
+
+def tf_get_col_order(ctx, K):
+    out = np.empty(int(K), dtype=np.int32)
+    _check(ctx, lib().tf_get_col_order(ctx, _np(out)))
+    return out
+
+
+def tf_loss(ctx):
+    l, r = ctypes.c_double(), ctypes.c_double()
+    _check(ctx, lib().tf_loss(ctx, ctypes.byref(l), ctypes.byref(r)))
+    return l.value, r.value
+
+
+def tf_predict(ctx, d_idx, d_out):
+    _check(ctx, lib().tf_predict(ctx, int(d_idx.shape[0]), _dev(d_idx), _dev(d_out)))
+
+
+def tf_get_factor(ctx, n, I, K):
+    out = np.empty((int(I), int(K)), dtype=np.float64)
+    _check(ctx, lib().tf_get_factor(ctx, int(n), _np(out)))
+    return out
+
+
+def tf_set_factor(ctx, n, A):
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    _check(ctx, lib().tf_set_factor(ctx, int(n), _np(A)))
+
+
+def tf_resync(ctx):
+    _check(ctx, lib().tf_resync(ctx))
+
+
+def tf_get_residual(ctx, nnz):
+    out = np.empty(int(nnz), dtype=np.float64)
+    _check(ctx, lib().tf_get_residual(ctx, _np(out)))
+    return out
+
+
+def tf_get_csr(ctx, n, I, nnz):
+    rp = np.empty(int(I) + 1, dtype=np.int64)
+    pm = np.empty(int(nnz), dtype=np.int32)
+    _check(ctx, lib().tf_get_csr(ctx, int(n), _np(rp), _np(pm)))
+    return rp, pm
+
+
+def tf_profile(ctx, enable=True):
+    _check(ctx, lib().tf_profile(ctx, 1 if enable else 0))
+
+
+def tf_profile_read(ctx) -> tf_kstats:
+    s = tf_kstats()
+    _check(ctx, lib().tf_profile_read(ctx, ctypes.byref(s)))
+    return s
+
+
+def tf_plan_rows(rowptr, strategy=TF_STRATEGY_SKEW, lane_nnz=8, split_threshold=4096,
+                 chunk_nnz=2048) -> tf_plan_summary:
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    s = tf_plan_summary()
+    _check(None, lib().tf_plan_rows(_np(rowptr), int(rowptr.shape[0] - 1), int(strategy),
+                                    int(lane_nnz), int(split_threshold), int(chunk_nnz),
+                                    ctypes.byref(s)))
+    return s
+
+
+def declared_symbols(header: str = HEADER):
+    """Names of the functions include/tf.h declares."""
+    import re
+    text = open(header).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tf_[a-z0-9_]+)\s*\(", text)))
