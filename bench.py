@@ -1,0 +1,204 @@
+"""Throughput of SALS sweeps on one MI355X (gfx950).
+
+One step is one sweep (outer iteration of Algorithm 1, arXiv:1410.5209) over
+the whole synthetic tensor: ceil(K/C) splits x T_in inner iterations x N mode
+passes.  The metric is nnz*C updates per second: every sweep folds each
+(observed entry, column) pair into its row's update T_in times per mode, i.e.
+nnz * K * T_in * N updates per sweep.
+
+Default workload: 3-way tensor, 1M x 1M x 1M, 1e8 uniform entries (the shape
+of the paper's synthetic S2), rank-20 ground truth mapped to [1, 5] plus
+N(0, 0.25^2) noise; K = 100, lambda = 1, C = 10, T_in = 2; FP32 factors,
+residual and Gram accumulation, FP64 Cholesky.  Inputs are generated on the
+host and resident in HBM before timing starts.
+
+Besides the JSON line fields the driver needs, it reports:
+  roofline     achieved algorithmic GB/s of the row-accumulation kernel (HIP
+               events around each launch on the library's stream) vs 8 TB/s;
+               traffic = DRAM bytes per launch from rocprofv3 counters when the
+               counter file matches the current kernel source, else null
+  cpu_baseline the FP64 oracle timed on the host cores (rank 0 only) on one
+               split of the same recipe at quarter size (same row lengths)
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "nnz·C updates/s per SALS/CDTF sweep, % HBM roofline; fold-in p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1410_5209_amd/csrc/k_rows.inc.h", "paper_1410_5209_amd/csrc/dev_common.h",
+                  "paper_1410_5209_amd/csrc/tf_internal.h"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_per_launch(workload: str):
+    """DRAM bytes per accumulation launch from the committed counter summary,
+    if it was taken from the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"k_accum_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, scale=4):
+    """The oracle as it stands, on one split of the same recipe at 1/scale size
+    (mode lengths and entries both divided by `scale`, so every row keeps the
+    full workload's mean length; K, C, T_in, lambda unchanged)."""
+    import synth
+    from oracle import oracle as orc
+    r = w.replica(w.I // scale, w.nnz // scale)
+    idx, x = synth.make_tensor(r)[:2]
+    t0 = time.perf_counter()
+    o = orc.Oracle([r.I] * r.N, idx, x, r.K, r.lam)
+    o.init_factors(2, True)
+    t_setup = time.perf_counter() - t0
+    cols = list(range(min(r.C, r.K)))
+    t0 = time.perf_counter()
+    o.split(cols, r.T_in)
+    dt = time.perf_counter() - t0
+    updates = idx.shape[0] * len(cols) * r.T_in * r.N
+    del o
+    return {"value": updates / dt, "unit": "nnz·C updates/s", "cores": orc.get_threads(),
+            "kind": "oracle",
+            "sample": f"one split (C={len(cols)}, T_in={r.T_in}) of the same recipe at 1/{scale} size "
+                      f"(I={r.I} per mode, {idx.shape[0]} entries, K={r.K}): {updates} updates in "
+                      f"{dt:.2f} s; setup {t_setup:.1f} s untimed"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="sals-3way-1m-fp32")
+    ap.add_argument("--strategy", type=int, default=1)
+    ap.add_argument("--lane-nnz", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the row-sharded multi-GPU design is described, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1410_5209_amd import tf
+    from paper_1410_5209_amd.model import SparseCP
+
+    w = synth.WORKLOADS[args.workload]
+    dims = [w.I] * w.N
+    t0 = time.perf_counter()
+    data = synth.make_tensor(w)
+    idx, x = data[0], data[1]
+    log(f"generated {idx.shape[0]} entries in {time.perf_counter() - t0:.1f} s")
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    m = SparseCP(dims, idx, x, w.K, w.lam, precision=w.prec, strategy=args.strategy,
+                 lane_nnz=args.lane_nnz)
+    torch.cuda.synchronize()
+    log(f"tf_init {time.perf_counter() - t0:.1f} s")
+
+    if args.calibrate_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    for s in range(args.warmup):
+        m.sweep(w.C, w.T_in)
+        log(f"warmup sweep {s} done")
+    torch.cuda.synchronize()
+
+    m.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        m.sweep(w.C, w.T_in)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ks = m.profile_read()
+    m.profile(False)
+    loss, rmse = m.loss()
+    log(f"timed {args.steps} sweeps in {dt:.3f} s; loss {loss:.6g} rmse {rmse:.6g}")
+
+    nnz = m.nnz
+    ms = dt * 1000.0 / args.steps
+    updates = nnz * w.K * w.T_in * w.N
+    value = updates / (ms / 1000.0)
+    avg_ms = ks.total_ms / max(ks.launches, 1)
+    bytes_per_launch = ks.alg_bytes / max(ks.launches, 1)
+    achieved = (ks.alg_bytes / 1e9) / (ks.total_ms / 1000.0) if ks.total_ms > 0 else 0.0
+    traffic = traffic_per_launch(args.workload)
+    m.close()
+    del m
+    torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the oracle on one split")
+        del idx, x
+        cpu = cpu_baseline(w)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "nnz·C updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32", "bf16": "bf16-storage/f32"}[w.prec],
+        "data": "synthetic",
+        "config": {"workload": w.name, "N": w.N, "I": w.I, "nnz": nnz, "K": w.K, "C": w.C,
+                   "T_in": w.T_in, "lambda": w.lam, "precision": w.prec,
+                   "strategy": "skew" if args.strategy == 1 else "plain",
+                   "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "kernel": "k_accum (gather + Gram accumulation)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "launches": ks.launches, "avg_launch_ms": avg_ms,
+                     "alg_bytes_per_launch": bytes_per_launch,
+                     "kernel_share_of_sweep": ks.total_ms / (dt * 1000.0)},
+        "cpu_baseline": cpu,
+        "loss_after": loss,
+        "train_rmse_after": rmse,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

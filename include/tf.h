@@ -67,13 +67,11 @@ typedef struct tf_options {
     int32_t strategy;          /* TF_STRATEGY_* (default TF_STRATEGY_SKEW) */
     uint64_t seed;             /* factor initialisation seed (default 2) */
     void *stream;              /* hipStream_t, NULL = null stream */
-    int32_t lane_nnz;          /* SKEW: target nonzeros per lane (0 = 8) */
+    int32_t lane_nnz;          /* SKEW: target nonzeros per lane (0 = 2) */
     int32_t split_threshold;   /* SKEW: rows longer than this are split
                                   (0 = 4096) */
     int32_t chunk_nnz;         /* SKEW: nonzeros per chunk of a split row
                                   (0 = 2048) */
-    int32_t slab_pad;          /* slab row stride alignment in bytes:
-                                  16 (default) or 64 */
 } tf_options;
 
 typedef struct tf_ctx tf_ctx;
@@ -174,6 +172,9 @@ typedef struct tf_kstats {
     double total_ms;        /* summed event time */
     double alg_bytes;       /* summed algorithmic bytes of those launches */
     int64_t sweeps;
+    int64_t first_launches; /* of which first passes of a split (residual */
+    double first_ms;        /*   brought up to date in the same walk)     */
+    double first_bytes;
 } tf_kstats;
 tf_status tf_profile(tf_ctx *ctx, int32_t enable);        /* 1 on, 0 off; resets */
 tf_status tf_profile_read(tf_ctx *ctx, tf_kstats *out);    /* synchronises */

@@ -98,15 +98,91 @@ __device__ __forceinline__ void load_row(const bf16 *__restrict__ p, TA (&out)[C
     }
 }
 
+// Same as load_row for a row start that is only 8-byte aligned (the
+// pending-column segment of an interleaved slab row).
+template <int CP, typename TA>
+__device__ __forceinline__ void load_row8(const double *__restrict__ p, TA (&out)[CP])
+{
+#pragma unroll
+    for (int c = 0; c < CP; ++c) out[c] = (TA)p[c];
+}
+template <int CP, typename TA>
+__device__ __forceinline__ void load_row8(const float *__restrict__ p, TA (&out)[CP])
+{
+    const float2 *q = reinterpret_cast<const float2 *>(p);
+#pragma unroll
+    for (int v = 0; v < (CP + 1) / 2; ++v) {
+        float2 t = q[v];
+        out[2 * v] = (TA)t.x;
+        if (2 * v + 1 < CP) out[2 * v + 1] = (TA)t.y;
+    }
+}
+template <int CP, typename TA>
+__device__ __forceinline__ void load_row8(const bf16 *__restrict__ p, TA (&out)[CP])
+{
+    const uint2 *q = reinterpret_cast<const uint2 *>(p);
+#pragma unroll
+    for (int v = 0; v < (CP + 3) / 4; ++v) {
+        uint2 t = q[v];
+        uint32_t w[2] = {t.x, t.y};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (4 * v + 2 * h < CP) out[4 * v + 2 * h] = (TA)__uint_as_float(w[h] << 16);
+            if (4 * v + 2 * h + 1 < CP) out[4 * v + 2 * h + 1] = (TA)__uint_as_float(w[h] & 0xffff0000u);
+        }
+    }
+}
+
 template <typename T> __device__ __forceinline__ T stream_load(const T *p) { return __builtin_nontemporal_load(p); }
 template <typename T> __device__ __forceinline__ void stream_store(T v, T *p) { __builtin_nontemporal_store(v, p); }
 
-// Sum over the G lanes of a group (G a power of two, groups aligned).
-template <typename T>
-__device__ __forceinline__ T group_sum(T v, int G)
+// Cross-lane moves inside a row of 16 lanes (DPP, no LDS traffic).
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v)
 {
-    for (int m = 1; m < G; m <<= 1) v += __shfl_xor(v, m, 64);
-    return v;
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// In-place sum over the G lanes of each aligned group (G a power of two, all
+// 64 lanes active).  Inside 16 lanes: quad swaps (xor 1, xor 2), then the
+// half-row and row mirrors, each pairing lanes from the two halves of the
+// block summed so far; across rows: lane shuffles.  Every lane ends with its
+// group's sum.
+template <int NE, typename T>
+__device__ __forceinline__ void group_reduce(T (&v)[NE], int G)
+{
+    if (G >= 2) {
+#pragma unroll
+        for (int e = 0; e < NE; ++e) v[e] += dpp_mov<0xB1>(v[e]);   // quad_perm 1,0,3,2
+    }
+    if (G >= 4) {
+#pragma unroll
+        for (int e = 0; e < NE; ++e) v[e] += dpp_mov<0x4E>(v[e]);   // quad_perm 2,3,0,1
+    }
+    if (G >= 8) {
+#pragma unroll
+        for (int e = 0; e < NE; ++e) v[e] += dpp_mov<0x141>(v[e]);  // row_half_mirror
+    }
+    if (G >= 16) {
+#pragma unroll
+        for (int e = 0; e < NE; ++e) v[e] += dpp_mov<0x140>(v[e]);  // row_mirror
+    }
+    if (G >= 32) {
+#pragma unroll
+        for (int e = 0; e < NE; ++e) v[e] += __shfl_xor(v[e], 16, 64);
+    }
+    if (G >= 64) {
+#pragma unroll
+        for (int e = 0; e < NE; ++e) v[e] += __shfl_xor(v[e], 32, 64);
+    }
 }
 
 }  // namespace tfk

@@ -10,6 +10,10 @@
 //   the residual up to date: it subtracts the columns of the previous split
 //   with their final values (eq. (SALS_R)) and adds the columns of this split
 //   with their values at the start of the split (R-hat, Algorithm 1).
+//   A factor row of a split lives in one interleaved slab row
+//   [W: current | P: previous split, final | S: this split, at its start]
+//   inside a 128-byte line, so every entry costs one line request per other
+//   mode in every pass (random line requests, not bytes, bound this kernel).
 // k_solve: one lane per row solves (B + lambda_i I) a = c in FP64 by
 //   Cholesky (text after Theorem 1) and writes a into the mode's slab.
 #pragma once
@@ -62,7 +66,7 @@ __global__ __launch_bounds__(256) void k_accum(AccumArgs a)
         if (row >= 0) {
             load_row<CP>(reinterpret_cast<const TS *>(a.Sown) + (int64_t)row * ld, own_s);
             if (a.has_pend)
-                load_row<CP>(reinterpret_cast<const TS *>(a.Pown) + (int64_t)row * ld, own_p);
+                load_row8<CP>(reinterpret_cast<const TS *>(a.Pown) + (int64_t)row * ld, own_p);
             else {
 #pragma unroll
                 for (int c = 0; c < CP; ++c) own_p[c] = TA(0);
@@ -78,38 +82,92 @@ __global__ __launch_bounds__(256) void k_accum(AccumArgs a)
     for (int e = 0; e < NE; ++e) acc[e] = TA(0);
 
     int64_t j = beg + sub;
-    int32_t ii[NO];
-    TR rh = TR(0);
-    if (j < end) {
-#pragma unroll
-        for (int l = 0; l < NO; ++l) ii[l] = stream_load(a.oidx[l] + j);
-        rh = stream_load(rhat + j);
-    }
-    for (; j < end; j += G) {
-        int32_t cur[NO];
-#pragma unroll
-        for (int l = 0; l < NO; ++l) cur[l] = ii[l];
-        TR rcur = rh;
-        const int64_t jn = j + G;
-        if (jn < end) {  // prefetch the next entry's indices and residual
-#pragma unroll
-            for (int l = 0; l < NO; ++l) ii[l] = stream_load(a.oidx[l] + jn);
-            rh = stream_load(rhat + jn);
-        }
+    if constexpr (!FIRST) {
+        // Software pipeline: the factor rows of the next entry are requested
+        // before the current entry is folded in, and the indices one entry
+        // further ahead, so a lane keeps gathers in flight while it computes.
+        int32_t ii[NO];
+        TR rh = TR(0);
         TA w[NO][CP];
+        if (j < end) {
 #pragma unroll
-        for (int l = 0; l < NO; ++l)
-            load_row<CP>(reinterpret_cast<const TS *>(a.W[l]) + (int64_t)cur[l] * ld, w[l]);
-        TA p[CP];
+            for (int l = 0; l < NO; ++l) ii[l] = stream_load(a.oidx[l] + j);
+            rh = stream_load(rhat + j);
 #pragma unroll
-        for (int c = 0; c < CP; ++c) p[c] = w[0][c];
+            for (int l = 0; l < NO; ++l)
+                load_row<CP>(reinterpret_cast<const TS *>(a.W[l]) + (int64_t)ii[l] * ld, w[l]);
+        }
+        int64_t jn = j + G;
+        int32_t in_[NO];
+        TR rn = TR(0);
+        if (jn < end) {
 #pragma unroll
-        for (int l = 1; l < NO; ++l)
+            for (int l = 0; l < NO; ++l) in_[l] = stream_load(a.oidx[l] + jn);
+            rn = stream_load(rhat + jn);
+        }
+        while (j < end) {
+            TA p[CP];
 #pragma unroll
-            for (int c = 0; c < CP; ++c) p[c] *= w[l][c];
+            for (int c = 0; c < CP; ++c) p[c] = w[0][c];
+#pragma unroll
+            for (int l = 1; l < NO; ++l)
+#pragma unroll
+                for (int c = 0; c < CP; ++c) p[c] *= w[l][c];
+            const TA r = (TA)rh;
+            if (jn < end) {
+                rh = rn;
+#pragma unroll
+                for (int l = 0; l < NO; ++l)
+                    load_row<CP>(reinterpret_cast<const TS *>(a.W[l]) + (int64_t)in_[l] * ld, w[l]);
+                const int64_t jnn = jn + G;
+                if (jnn < end) {
+#pragma unroll
+                    for (int l = 0; l < NO; ++l) in_[l] = stream_load(a.oidx[l] + jnn);
+                    rn = stream_load(rhat + jnn);
+                }
+            }
+            int e = 0;
+#pragma unroll
+            for (int c1 = 0; c1 < CP; ++c1)
+#pragma unroll
+                for (int c2 = c1; c2 < CP; ++c2) acc[e++] += p[c1] * p[c2];
+#pragma unroll
+            for (int c = 0; c < CP; ++c) acc[e++] += r * p[c];
+            j = jn;
+            jn += G;
+        }
+    } else {
+        int32_t ii[NO];
+        TR rh = TR(0);
+        if (j < end) {
+#pragma unroll
+            for (int l = 0; l < NO; ++l) ii[l] = stream_load(a.oidx[l] + j);
+            rh = stream_load(rhat + j);
+        }
+        for (; j < end; j += G) {
+            int32_t cur[NO];
+#pragma unroll
+            for (int l = 0; l < NO; ++l) cur[l] = ii[l];
+            TR rcur = rh;
+            const int64_t jn = j + G;
+            if (jn < end) {  // prefetch the next entry's indices and residual
+#pragma unroll
+                for (int l = 0; l < NO; ++l) ii[l] = stream_load(a.oidx[l] + jn);
+                rh = stream_load(rhat + jn);
+            }
+            TA w[NO][CP];
+#pragma unroll
+            for (int l = 0; l < NO; ++l)
+                load_row<CP>(reinterpret_cast<const TS *>(a.W[l]) + (int64_t)cur[l] * ld, w[l]);
+            TA p[CP];
+#pragma unroll
+            for (int c = 0; c < CP; ++c) p[c] = w[0][c];
+#pragma unroll
+            for (int l = 1; l < NO; ++l)
+#pragma unroll
+                for (int c = 0; c < CP; ++c) p[c] *= w[l][c];
 
-        TA r = (TA)rcur;
-        if constexpr (FIRST) {
+            // R-hat of this split from the previous split's residual state
             TA tp[CP], ts[CP];
 #pragma unroll
             for (int c = 0; c < CP; ++c) { tp[c] = own_p[c]; ts[c] = own_s[c]; }
@@ -117,7 +175,7 @@ __global__ __launch_bounds__(256) void k_accum(AccumArgs a)
             for (int l = 0; l < NO; ++l) {
                 if (a.has_pend) {
                     TA v[CP];
-                    load_row<CP>(reinterpret_cast<const TS *>(a.P[l]) + (int64_t)cur[l] * ld, v);
+                    load_row8<CP>(reinterpret_cast<const TS *>(a.P[l]) + (int64_t)cur[l] * ld, v);
 #pragma unroll
                     for (int c = 0; c < CP; ++c) tp[c] *= v[c];
                 }
@@ -134,21 +192,20 @@ __global__ __launch_bounds__(256) void k_accum(AccumArgs a)
             TA dr = TA(0), ds = TA(0);
 #pragma unroll
             for (int c = 0; c < CP; ++c) { dr += tp[c]; ds += ts[c]; }
-            r = (r - dr) + ds;
+            const TA r = ((TA)rcur - dr) + ds;
             stream_store((TR)r, rhat + j);
-        }
 
-        int e = 0;
+            int e = 0;
 #pragma unroll
-        for (int c1 = 0; c1 < CP; ++c1)
+            for (int c1 = 0; c1 < CP; ++c1)
 #pragma unroll
-            for (int c2 = c1; c2 < CP; ++c2) acc[e++] += p[c1] * p[c2];
+                for (int c2 = c1; c2 < CP; ++c2) acc[e++] += p[c1] * p[c2];
 #pragma unroll
-        for (int c = 0; c < CP; ++c) acc[e++] += r * p[c];
+            for (int c = 0; c < CP; ++c) acc[e++] += r * p[c];
+        }
     }
 
-#pragma unroll
-    for (int e = 0; e < NE; ++e) acc[e] = group_sum(acc[e], G);
+    group_reduce<NE>(acc, G);
 
     if (row >= 0 && sub == 0) {
         if constexpr (sizeof(TA) == 4) {

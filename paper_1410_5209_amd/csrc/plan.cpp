@@ -23,7 +23,7 @@ void plan_rows(const int64_t *rowptr, int64_t I, int strategy, int lane_nnz, int
                int chunk_nnz, HostPlan *out)
 {
     *out = HostPlan();
-    if (lane_nnz <= 0) lane_nnz = 8;
+    if (lane_nnz <= 0) lane_nnz = 2;
     if (split_threshold <= 0) split_threshold = 4096;
     if (chunk_nnz <= 0) chunk_nnz = 2048;
     auto cnt = [&](int64_t i) { return rowptr[i + 1] - rowptr[i]; };

@@ -110,23 +110,28 @@ tf_status ensure_gram(tf_ctx *c, int CP)
     return TF_OK;
 }
 
-int64_t slab_ld(const tf_ctx *c, int width)
+// Bytes reserved per slab row: three segments of up to kMaxC elements plus
+// alignment, rounded to whole 128-byte lines.
+constexpr size_t kSlabRowBytes = 384;
+
+// Segment width and row stride of the interleaved slabs for a given number
+// of columns: segments of whole 8-byte units (so W and S start 16-byte
+// aligned), rows padded to whole 128-byte lines so that no row straddles a
+// line it does not need.
+void slab_geometry(tf_ctx *c, int width)
 {
-    const int vw = vec_w(c->prec);
-    int64_t ld = (width + vw - 1) / vw * vw;
-    if (c->opt.slab_pad == 64) {
-        const int64_t per = 64 / (int64_t)ts_size(c->prec);
-        ld = (ld + per - 1) / per * per;
-    }
-    return ld;
+    const int64_t q = c->prec == P_BF16 ? 4 : 2;
+    const int64_t sw = (std::max(width, 1) + q - 1) / q * q;
+    const int64_t vw = vec_w(c->prec);
+    const int64_t need = std::max<int64_t>(3 * sw, 2 * sw + (sw + vw - 1) / vw * vw);
+    const int64_t per_line = 128 / (int64_t)ts_size(c->prec);
+    c->sw = sw;
+    c->ld = (need + per_line - 1) / per_line * per_line;
 }
 
-int64_t slab_cap_elems(const tf_ctx *c)
+const void *seg(const tf_ctx *c, const void *Z, int which)
 {
-    // widest slab row: kMaxC columns, padded to 64 bytes
-    const int64_t per = 64 / (int64_t)ts_size(c->prec);
-    const int64_t w = (kMaxC + per - 1) / per * per;
-    return std::max<int64_t>(w, kMaxC);
+    return static_cast<const char *>(Z) + (size_t)which * (size_t)c->sw * ts_size(c->prec);
 }
 
 void fill_accum_args(tf_ctx *c, int n, int npend, AccumArgs *a)
@@ -143,14 +148,14 @@ void fill_accum_args(tf_ctx *c, int n, int npend, AccumArgs *a)
     for (int l = 0; l < c->N; ++l) {
         if (l == n) continue;
         a->oidx[t] = md.oidx[t];
-        a->W[t] = c->m[l].W;
-        a->S[t] = c->m[l].S;
-        a->P[t] = c->m[l].P;
+        a->W[t] = seg(c, c->m[l].Z, 0);
+        a->P[t] = seg(c, c->m[l].Z, 1);
+        a->S[t] = seg(c, c->m[l].Z, 2);
         a->before[t] = l < n ? 1 : 0;
         ++t;
     }
-    a->Sown = md.S;
-    a->Pown = md.P;
+    a->Pown = seg(c, md.Z, 1);
+    a->Sown = seg(c, md.Z, 2);
     a->has_pend = npend > 0 ? 1 : 0;
     a->no = c->N - 1;
     a->ld = c->ld;
@@ -186,13 +191,12 @@ double alg_bytes(const tf_ctx *c, int n, int C, int npend, bool first)
     return b;
 }
 
-tf_status pack_all(tf_ctx *c, const int32_t *d_cols, int ncols, int width, bool into_p)
+tf_status pack_all(tf_ctx *c, const int32_t *d_cur, int ncur, const int32_t *d_pend, int npend)
 {
     for (int l = 0; l < c->N; ++l) {
         auto &md = c->m[l];
-        hipError_t e = into_p
-            ? pack_slab(c->prec, md.A, md.I, c->K, d_cols, ncols, width, c->ld, md.P, nullptr, c->stream)
-            : pack_slab(c->prec, md.A, md.I, c->K, d_cols, ncols, width, c->ld, md.S, md.W, c->stream);
+        hipError_t e = pack_slab(c->prec, md.A, md.I, c->K, d_cur, ncur, d_pend, npend, c->sw,
+                                 c->ld, md.Z, c->stream);
         if (e != hipSuccess) return CTX_FAIL(c, TF_E_DEVICE, "pack: %s", hipGetErrorString(e));
     }
     return TF_OK;
@@ -219,16 +223,14 @@ tf_status run_split(tf_ctx *c, const int32_t *cols, int ncols, int T_in)
     if (s != TF_OK) return s;
     const int npend = (int)c->pend.size();
     const bool fuse = npend <= CP;
-    const int width = std::max(CP, npend);
-    c->ld = slab_ld(c, width);
+    slab_geometry(c, std::max(CP, npend));
     if ((s = upload_cols(c, cols, ncols)) != TF_OK) return s;
     const int32_t *d_cur = c->d_cols;
     const int32_t *d_pend = c->d_cols + c->K;
 
     // slabs at the start of the split: S (snapshot) and W (working copy) hold
     // the split's columns, P the previous split's columns (final values)
-    if ((s = pack_all(c, d_cur, ncols, width, false)) != TF_OK) return s;
-    if (npend > 0 && (s = pack_all(c, d_pend, npend, width, true)) != TF_OK) return s;
+    if ((s = pack_all(c, d_cur, ncols, d_pend, npend)) != TF_OK) return s;
 
     if (!fuse) {  // bring every copy to R-hat of this split before the passes
         for (int n = 0; n < c->N; ++n) {
@@ -257,7 +259,7 @@ tf_status run_split(tf_ctx *c, const int32_t *cols, int ncols, int T_in)
                 if (c->profiling && e0 && e1) {
                     HIPCHK(c, hipEventRecord(e1, c->stream));
                     c->ev_pending.push_back(
-                        tf_ctx::Timed{e0, e1, alg_bytes(c, n, ncols, npend, first)});
+                        tf_ctx::Timed{e0, e1, alg_bytes(c, n, ncols, npend, first), first});
                 }
             }
             if (md.nsplit > 0)
@@ -267,7 +269,7 @@ tf_status run_split(tf_ctx *c, const int32_t *cols, int ncols, int T_in)
             sa.rowptr = md.rowptr;
             sa.I = md.I;
             sa.gram = c->gram;
-            sa.W = md.W;
+            sa.W = md.Z;
             sa.ld = c->ld;
             sa.lambda = c->lambda;
             sa.reg_mode = c->opt.reg_mode;
@@ -277,7 +279,7 @@ tf_status run_split(tf_ctx *c, const int32_t *cols, int ncols, int T_in)
     }
     for (int l = 0; l < c->N; ++l) {
         auto &md = c->m[l];
-        HIPCHK(c, unpack_slab(c->prec, md.W, md.I, c->K, d_cur, ncols, c->ld, md.A, c->stream));
+        HIPCHK(c, unpack_slab(c->prec, md.Z, md.I, c->K, d_cur, ncols, c->ld, md.A, c->stream));
     }
     c->pend.assign(cols, cols + ncols);
     return TF_OK;
@@ -321,13 +323,13 @@ tf_status ensure_partials(tf_ctx *c, int64_t n)
 // Sum of r^2 over all entries (and optionally r in input order).
 tf_status eval_residual(tf_ctx *c, double *d_rout, double *se_out)
 {
+    // the pending columns go into the W segment of the slabs
     const int npend = (int)c->pend.size();
-    const int width = std::max(npend, 1);
-    c->ld = std::max<int64_t>(slab_ld(c, width), 1);
+    slab_geometry(c, std::max(npend, 1));
     tf_status s;
     if (npend > 0) {
-        if ((s = upload_cols(c, c->pend.data(), 0)) != TF_OK) return s;
-        if ((s = pack_all(c, c->d_cols + c->K, npend, width, true)) != TF_OK) return s;
+        if ((s = upload_cols(c, c->pend.data(), npend)) != TF_OK) return s;
+        if ((s = pack_all(c, c->d_cols, npend, c->d_cols, 0)) != TF_OK) return s;
     }
     auto &m0 = c->m[0];
     EvalArgs a;
@@ -339,10 +341,10 @@ tf_status eval_residual(tf_ctx *c, double *d_rout, double *se_out)
     a.chunks = m0.chunks;
     for (int l = 1; l < c->N; ++l) {
         a.oidx[l - 1] = m0.oidx[l - 1];
-        a.P[l - 1] = c->m[l].P;
+        a.P[l - 1] = c->m[l].Z;
     }
     a.rhat = m0.rhat;
-    a.Pown = m0.P;
+    a.Pown = m0.Z;
     a.npend = npend;
     a.no = c->N - 1;
     a.ld = c->ld;
@@ -370,7 +372,7 @@ void destroy_ctx(tf_ctx *c)
         auto &md = c->m[n];
         dfree(md.rowptr); dfree(md.perm);
         for (int l = 0; l < kMaxModes - 1; ++l) dfree(md.oidx[l]);
-        dfree(md.rhat); dfree(md.A); dfree(md.W); dfree(md.S); dfree(md.P);
+        dfree(md.rhat); dfree(md.A); dfree(md.Z);
         dfree(md.tasks); dfree(md.items); dfree(md.chunks);
         dfree(md.split_rows); dfree(md.split_chunk_ptr);
     }
@@ -471,13 +473,9 @@ tf_status build_state(tf_ctx *c, const int32_t *d_idx, const double *d_vals)
         const bool zero = c->opt.first_factor_zero && n == 0;
         HIPCHK(c, init_factor(c->prec, md.A, md.I, c->K, c->opt.seed, offset, zero, st));
         offset += (uint64_t)md.I * (uint64_t)c->K;
-        const size_t slab = (size_t)md.I * (size_t)slab_cap_elems(c) * sf;
-        HIPCHK(c, hipMalloc(&md.W, slab));
-        HIPCHK(c, hipMalloc(&md.S, slab));
-        HIPCHK(c, hipMalloc(&md.P, slab));
-        HIPCHK(c, hipMemsetAsync(md.W, 0, slab, st));
-        HIPCHK(c, hipMemsetAsync(md.S, 0, slab, st));
-        HIPCHK(c, hipMemsetAsync(md.P, 0, slab, st));
+        const size_t slab = (size_t)md.I * kSlabRowBytes;
+        HIPCHK(c, hipMalloc(&md.Z, slab));
+        HIPCHK(c, hipMemsetAsync(md.Z, 0, slab, st));
         HIPCHK(c, hipMalloc(&md.rhat, (size_t)nnz * tr_size(c->prec)));
     }
     // residual r = x - reconstruction (exactly x when A^(1) = 0)
@@ -513,10 +511,9 @@ void tf_default_options(tf_options *opt)
     opt->strategy = TF_STRATEGY_SKEW;
     opt->seed = 2;
     opt->stream = nullptr;
-    opt->lane_nnz = 8;
+    opt->lane_nnz = 2;
     opt->split_threshold = 4096;
     opt->chunk_nnz = 2048;
-    opt->slab_pad = 16;
 }
 
 const char *tf_last_error(const tf_ctx *ctx)
@@ -553,9 +550,7 @@ tf_status tf_init(tf_ctx **out, int32_t N, const int64_t *dims, int64_t nnz, con
         return set_err(&g_init_err, TF_E_INVALID, "bad strategy");
     if (o.lane_nnz < 0 || o.split_threshold < 0 || o.chunk_nnz < 0)
         return set_err(&g_init_err, TF_E_INVALID, "negative tuning option");
-    if (o.slab_pad == 0) o.slab_pad = 16;
-    if (o.slab_pad != 16 && o.slab_pad != 64) return set_err(&g_init_err, TF_E_INVALID, "slab_pad must be 16 or 64");
-    if (o.lane_nnz == 0) o.lane_nnz = 8;
+    if (o.lane_nnz == 0) o.lane_nnz = 2;
     if (o.split_threshold == 0) o.split_threshold = 4096;
     if (o.chunk_nnz == 0) o.chunk_nnz = 2048;
 
@@ -791,6 +786,11 @@ tf_status tf_profile_read(tf_ctx *ctx, tf_kstats *out)
         ctx->kstats.launches += 1;
         ctx->kstats.total_ms += ms;
         ctx->kstats.alg_bytes += t.bytes;
+        if (t.first) {
+            ctx->kstats.first_launches += 1;
+            ctx->kstats.first_ms += ms;
+            ctx->kstats.first_bytes += t.bytes;
+        }
         ctx->ev_free.push_back(t.a);
         ctx->ev_free.push_back(t.b);
     }

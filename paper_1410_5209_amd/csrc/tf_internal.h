@@ -129,8 +129,8 @@ hipError_t factor_to_f64(int prec, const void *A, int64_t n, double *out, hipStr
 hipError_t factor_from_f64(int prec, const double *in, int64_t n, void *A, hipStream_t st);
 
 // ---------------------------------------------------------------- slabs
-hipError_t pack_slab(int prec, const void *A, int64_t I, int K, const int32_t *cols, int ncols,
-                     int CP, int64_t ld, void *out1, void *out2, hipStream_t st);
+hipError_t pack_slab(int prec, const void *A, int64_t I, int K, const int32_t *cur, int ncur,
+                     const int32_t *pend, int npend, int64_t sw, int64_t ld, void *Z, hipStream_t st);
 hipError_t unpack_slab(int prec, const void *W, int64_t I, int K, const int32_t *cols, int ncols,
                        int64_t ld, void *A, hipStream_t st);
 
@@ -186,7 +186,7 @@ struct tf_ctx {
         int32_t *oidx[tfk::kMaxModes - 1] = {nullptr};
         void *rhat = nullptr;          // nnz (TR)
         void *A = nullptr;             // I x K (TS)
-        void *W = nullptr, *S = nullptr, *P = nullptr;  // slabs I x ld (TS)
+        void *Z = nullptr;             // interleaved slab rows [W | P | S], I x ld (TS)
         tfk::Task *tasks = nullptr;
         int32_t ntasks = 0;
         int32_t *items = nullptr;
@@ -198,7 +198,8 @@ struct tf_ctx {
         std::vector<int64_t> h_rowptr;
     } m[tfk::kMaxModes];
 
-    int64_t ld = 0;           // slab row stride (elements)
+    int64_t ld = 0;           // slab row stride (elements, 128-byte multiple)
+    int64_t sw = 0;           // slab segment width (elements)
     int slab_cp = 0;          // compute width the slabs are sized for
     void *gram = nullptr;     // max_I x gram_stride(slab_cp) (TA)
     void *gpart = nullptr;    // max_chunks x gram_stride(slab_cp) (TA)
@@ -215,7 +216,7 @@ struct tf_ctx {
 
     bool profiling = false;
     std::vector<hipEvent_t> ev_free;
-    struct Timed { hipEvent_t a, b; double bytes; };
+    struct Timed { hipEvent_t a, b; double bytes; bool first; };
     std::vector<Timed> ev_pending;
     tf_kstats kstats{};
 

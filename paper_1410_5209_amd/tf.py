@@ -12,7 +12,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtfsals.so")
+LIB_PATH = os.environ.get("TFSALS_LIB") or os.path.join(_HERE, "libtfsals.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "tf.h")
 
 TF_OK, TF_E_INVALID, TF_E_NOMEM, TF_E_DEVICE, TF_E_NUMERIC, TF_E_UNSUPPORTED, TF_E_BUSY, TF_E_STATE = range(8)
@@ -26,13 +26,14 @@ class tf_options(ctypes.Structure):
                 ("reg_mode", ctypes.c_int32), ("first_factor_zero", ctypes.c_int32),
                 ("strategy", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("stream", ctypes.c_void_p), ("lane_nnz", ctypes.c_int32),
-                ("split_threshold", ctypes.c_int32), ("chunk_nnz", ctypes.c_int32),
-                ("slab_pad", ctypes.c_int32)]
+                ("split_threshold", ctypes.c_int32), ("chunk_nnz", ctypes.c_int32)]
 
 
 class tf_kstats(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
-                ("alg_bytes", ctypes.c_double), ("sweeps", ctypes.c_int64)]
+                ("alg_bytes", ctypes.c_double), ("sweeps", ctypes.c_int64),
+                ("first_launches", ctypes.c_int64), ("first_ms", ctypes.c_double),
+                ("first_bytes", ctypes.c_double)]
 
 
 class tf_plan_summary(ctypes.Structure):
@@ -201,7 +202,7 @@ def tf_profile_read(ctx) -> tf_kstats:
     return s
 
 
-def tf_plan_rows(rowptr, strategy=TF_STRATEGY_SKEW, lane_nnz=8, split_threshold=4096,
+def tf_plan_rows(rowptr, strategy=TF_STRATEGY_SKEW, lane_nnz=2, split_threshold=4096,
                  chunk_nnz=2048) -> tf_plan_summary:
     rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
     s = tf_plan_summary()

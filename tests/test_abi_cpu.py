@@ -21,7 +21,7 @@ def test_options_struct_matches_header_defaults():
     o = tf.tf_default_options()
     assert o.size == ctypes.sizeof(tf.tf_options) == 56
     assert (o.precision, o.reg_mode, o.first_factor_zero, o.strategy, o.seed) == (1, 0, 1, 1, 2)
-    assert (o.lane_nnz, o.split_threshold, o.chunk_nnz, o.slab_pad) == (8, 4096, 2048, 16)
+    assert (o.lane_nnz, o.split_threshold, o.chunk_nnz) == (2, 4096, 2048)
 
 
 def _rowptr(counts):
