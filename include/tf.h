@@ -165,6 +165,98 @@ tf_status tf_get_residual(tf_ctx *ctx, double *h);
 tf_status tf_get_csr(tf_ctx *ctx, int32_t n, int64_t *h_rowptr, int32_t *h_perm);
 
 /* ------------------------------------------------------------------ */
+/* Fold-in: new rows of one mode solved against the resident factors without
+ * changing the model (a use of the row update the paper does not make).  A
+ * request is the row's observed entries: for each, the indices of the other
+ * modes (ascending mode order) and the value.
+ *   TF_FOLDIN_FULL: eq. (ALS) for the row, a = (B + lambda_i I_K)^-1 c with c
+ *                   built from the values; FP32 (FP64 in FP64 mode) Gram,
+ *                   FP64 Cholesky; K <= 128.
+ *   TF_FOLDIN_CDTF: `sweeps` passes of the C = 1 update over k = 0..K-1
+ *                   starting from a = 0 (CDTF, Section 3.1); FP64 sums.
+ * lambda_i = lambda, or lambda * m in reg_mode 1.  An empty request gives 0. */
+#define TF_FOLDIN_FULL 0
+#define TF_FOLDIN_CDTF 1
+
+/*
+ * tf_foldin -- a batch of fold-in requests, synchronously.
+ *   mode      0 <= mode < N
+ *   nreq      >= 0; h_req_ptr host[nreq + 1] entry offsets (non-decreasing,
+ *             h_req_ptr[0] = 0)
+ *   d_idx     device, total x (N - 1) int32, total = h_req_ptr[nreq]
+ *   d_vals    device, total FP64
+ *   d_rows    device, nreq x K FP64 output
+ * Every request is solved by its own workgroup, so its result does not
+ * depend on the rest of the batch.  TF_E_INVALID for a bad index or value
+ * (message names the entry); TF_E_NUMERIC for a non-positive pivot (that
+ * row is 0); TF_E_UNSUPPORTED for TF_FOLDIN_FULL with K > 128.
+ */
+tf_status tf_foldin(tf_ctx *ctx, int32_t mode, int32_t nreq, const int64_t *h_req_ptr,
+                    const int32_t *d_idx, const double *d_vals, int32_t method, int32_t sweeps,
+                    double *d_rows);
+
+/* ------------------------------------------------------------------ */
+/* Fold-in serving: requests arrive one at a time from any host thread; a
+ * scheduler packs whatever is queued into a batch when a stream slot is free
+ * and the batch's device bytes fit that slot's share of the memory budget
+ * (continuous batching), so batches overlap on the GPU across streams.
+ * The resident factors must not change while a server is open. */
+typedef struct tf_serve_opts {
+    uint32_t size;         /* sizeof(tf_serve_opts) */
+    int32_t mode;          /* mode of the new rows (default 0) */
+    int32_t method;        /* TF_FOLDIN_* (default TF_FOLDIN_FULL) */
+    int32_t sweeps;        /* CDTF sweeps (default 3) */
+    int32_t streams;       /* stream slots, >= 1 (default 2) */
+    int32_t max_batch;     /* requests per batch (default 512) */
+    int32_t queue_cap;     /* queued requests before TF_E_BUSY (default 65536) */
+    int64_t mem_budget;    /* device bytes for in-flight batches (default 1 GiB),
+                              split evenly over the stream slots */
+} tf_serve_opts;
+
+typedef struct tf_request {
+    int32_t m;             /* entries */
+    const int32_t *h_idx;  /* host, m x (N - 1) */
+    const double *h_vals;  /* host, m */
+} tf_request;
+
+typedef struct tf_req_stats {
+    double latency_us;     /* submit -> result on the host */
+    double queue_us;       /* submit -> batch launched */
+    int32_t batch_size;    /* requests in its batch */
+    int32_t status;        /* TF_OK or TF_E_NUMERIC */
+} tf_req_stats;
+
+typedef struct tf_serve_stats {
+    int64_t completed, batches, busy_rejects, max_queue;
+    double p50_us, p90_us, p99_us, p999_us, max_us, mean_us;
+    double solves_per_s;   /* completed / (last completion - first submit) */
+    double mean_batch;
+} tf_serve_stats;
+
+typedef struct tf_server tf_server;
+
+void tf_serve_default_options(tf_serve_opts *opt);
+/* Starts the scheduler and completion threads.  NULL opts = defaults. */
+tf_status tf_serve_open(tf_ctx *ctx, const tf_serve_opts *opts, tf_server **out);
+/* Copies the request (caller may free it on return).  TF_E_BUSY when the
+ * queue is full; TF_E_INVALID for m < 0 or a request whose device bytes
+ * exceed one slot's share of the budget.  Thread-safe. */
+tf_status tf_serve_submit(tf_server *srv, const tf_request *req, uint64_t *ticket);
+/* Blocks until the ticket's row is done; h_row host[K] (may be NULL), st may
+ * be NULL.  A ticket can be waited once.  Thread-safe. */
+tf_status tf_serve_wait(tf_server *srv, uint64_t ticket, double *h_row, tf_req_stats *st);
+/* Load generator: submits reqs[i] at h_arrival_s[i] seconds after the call
+ * (non-decreasing), retrying while the queue is full; tickets[i] receives
+ * each ticket.  Returns once all are submitted. */
+tf_status tf_serve_replay(tf_server *srv, int64_t nreq, const double *h_arrival_s,
+                          const tf_request *reqs, uint64_t *tickets);
+/* Latency percentiles over the requests completed since open (or reset). */
+tf_status tf_serve_report(tf_server *srv, tf_serve_stats *out);
+tf_status tf_serve_reset_stats(tf_server *srv);
+/* Waits for queued and in-flight requests, then stops the threads. */
+void tf_serve_close(tf_server *srv);
+
+/* ------------------------------------------------------------------ */
 /* Kernel timing: HIP events around every launch of the row-accumulation
  * kernel (the one that gathers factor rows and builds the Gram matrices). */
 typedef struct tf_kstats {

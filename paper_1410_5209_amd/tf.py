@@ -42,6 +42,34 @@ class tf_plan_summary(ctypes.Structure):
                 ("rows_by_lanes", ctypes.c_int64 * 7)]
 
 
+class tf_serve_opts(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint32), ("mode", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("sweeps", ctypes.c_int32), ("streams", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("queue_cap", ctypes.c_int32),
+                ("mem_budget", ctypes.c_int64)]
+
+
+class tf_request(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("h_idx", ctypes.c_void_p), ("h_vals", ctypes.c_void_p)]
+
+
+class tf_req_stats(ctypes.Structure):
+    _fields_ = [("latency_us", ctypes.c_double), ("queue_us", ctypes.c_double),
+                ("batch_size", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+
+class tf_serve_stats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("busy_rejects", ctypes.c_int64), ("max_queue", ctypes.c_int64),
+                ("p50_us", ctypes.c_double), ("p90_us", ctypes.c_double),
+                ("p99_us", ctypes.c_double), ("p999_us", ctypes.c_double),
+                ("max_us", ctypes.c_double), ("mean_us", ctypes.c_double),
+                ("solves_per_s", ctypes.c_double), ("mean_batch", ctypes.c_double)]
+
+
+TF_FOLDIN_FULL, TF_FOLDIN_CDTF = 0, 1
+
+
 class TFError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"tf status {status}: {msg}")
@@ -80,10 +108,23 @@ def lib():
         L.tf_profile.argtypes = [P, i32]
         L.tf_profile_read.argtypes = [P, ctypes.POINTER(tf_kstats)]
         L.tf_plan_rows.argtypes = [P, i64, i32, i32, i32, i32, ctypes.POINTER(tf_plan_summary)]
+        L.tf_foldin.argtypes = [P, i32, i32, P, P, P, i32, i32, P]
+        L.tf_serve_default_options.argtypes = [ctypes.POINTER(tf_serve_opts)]
+        L.tf_serve_default_options.restype = None
+        L.tf_serve_open.argtypes = [P, ctypes.POINTER(tf_serve_opts), ctypes.POINTER(P)]
+        L.tf_serve_submit.argtypes = [P, ctypes.POINTER(tf_request), ctypes.POINTER(ctypes.c_uint64)]
+        L.tf_serve_wait.argtypes = [P, ctypes.c_uint64, P, ctypes.POINTER(tf_req_stats)]
+        L.tf_serve_replay.argtypes = [P, i64, P, P, P]
+        L.tf_serve_report.argtypes = [P, ctypes.POINTER(tf_serve_stats)]
+        L.tf_serve_reset_stats.argtypes = [P]
+        L.tf_serve_close.argtypes = [P]
+        L.tf_serve_close.restype = None
         for name in ("tf_init", "tf_sweep", "tf_split", "tf_set_col_order", "tf_get_col_order",
                      "tf_loss", "tf_predict", "tf_get_factor", "tf_set_factor", "tf_resync",
                      "tf_get_residual", "tf_get_csr", "tf_profile", "tf_profile_read",
-                     "tf_plan_rows"):
+                     "tf_plan_rows", "tf_foldin", "tf_serve_open", "tf_serve_submit",
+                     "tf_serve_wait", "tf_serve_replay", "tf_serve_report",
+                     "tf_serve_reset_stats"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -210,6 +251,82 @@ def tf_plan_rows(rowptr, strategy=TF_STRATEGY_SKEW, lane_nnz=2, split_threshold=
                                     int(lane_nnz), int(split_threshold), int(chunk_nnz),
                                     ctypes.byref(s)))
     return s
+
+
+def tf_foldin(ctx, mode, h_req_ptr, d_idx, d_vals, method, sweeps, d_rows):
+    """h_req_ptr host int64 (nreq+1); d_idx device int32 (total, N-1); d_vals
+    device float64 (total,); d_rows device float64 (nreq, K)."""
+    h_req_ptr = np.ascontiguousarray(h_req_ptr, dtype=np.int64)
+    nreq = int(h_req_ptr.shape[0] - 1)
+    _check(ctx, lib().tf_foldin(ctx, int(mode), nreq, _np(h_req_ptr), _dev(d_idx), _dev(d_vals),
+                                int(method), int(sweeps), _dev(d_rows)))
+
+
+def tf_serve_default_options(**kw) -> tf_serve_opts:
+    o = tf_serve_opts()
+    lib().tf_serve_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def tf_serve_open(ctx, opts: tf_serve_opts | None = None):
+    srv = ctypes.c_void_p()
+    _check(ctx, lib().tf_serve_open(ctx, ctypes.byref(opts) if opts is not None else None,
+                                    ctypes.byref(srv)))
+    return srv
+
+
+def make_request(idx, vals):
+    """A tf_request over host arrays (kept alive by the caller)."""
+    r = tf_request()
+    r.m = int(vals.shape[0])
+    r.h_idx = idx.ctypes.data if r.m else None
+    r.h_vals = vals.ctypes.data if r.m else None
+    return r
+
+
+def tf_serve_submit(srv, req: tf_request):
+    t = ctypes.c_uint64()
+    st = lib().tf_serve_submit(srv, ctypes.byref(req), ctypes.byref(t))
+    if st != TF_OK:
+        raise TFError(st, "tf_serve_submit")
+    return t.value
+
+
+def tf_serve_wait(srv, ticket, K):
+    row = np.empty(int(K), dtype=np.float64)
+    st = tf_req_stats()
+    rc = lib().tf_serve_wait(srv, ctypes.c_uint64(ticket), _np(row), ctypes.byref(st))
+    if rc != TF_OK:
+        raise TFError(rc, "tf_serve_wait")
+    return row, st
+
+
+def tf_serve_replay(srv, arrival_s, reqs):
+    arrival_s = np.ascontiguousarray(arrival_s, dtype=np.float64)
+    n = len(reqs)
+    arr = (tf_request * n)(*reqs)
+    tickets = np.empty(n, dtype=np.uint64)
+    rc = lib().tf_serve_replay(srv, n, _np(arrival_s), ctypes.cast(arr, ctypes.c_void_p),
+                               _np(tickets))
+    if rc != TF_OK:
+        raise TFError(rc, "tf_serve_replay")
+    return tickets
+
+
+def tf_serve_report(srv) -> tf_serve_stats:
+    r = tf_serve_stats()
+    _check(None, lib().tf_serve_report(srv, ctypes.byref(r)))
+    return r
+
+
+def tf_serve_reset_stats(srv):
+    _check(None, lib().tf_serve_reset_stats(srv))
+
+
+def tf_serve_close(srv):
+    lib().tf_serve_close(srv)
 
 
 def declared_symbols(header: str = HEADER):

@@ -1,0 +1,223 @@
+"""Fold-in (new rows solved against resident factors) and the serving loop,
+on the GPU through the C ABI, against the FP64 oracle.
+
+Tolerances: FP64 within 1e-10 of the oracle (max-abs relative); FP32 within
+1e-4 (FP32 Gram accumulation of at most a few thousand terms).  Serving must
+give every request the same bits alone, in a mix, and through tf_foldin."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import note, pair, problem, rel_max
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests(dims, mode, sizes, seed):
+    N = len(dims)
+    other = [d for l, d in enumerate(dims) if l != mode]
+    ptr = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    total = int(ptr[-1])
+    oidx = np.stack([synth.uniform_ints(seed, 60 + t, total, other[t]) for t in range(N - 1)],
+                    axis=1).astype(np.int32) if total else np.zeros((0, N - 1), np.int32)
+    vals = synth.values(seed, [max(o, 1) for o in other], oidx, 2, 0, 0.1) if total else \
+        np.zeros(0)
+    return ptr, oidx.reshape(total, N - 1), vals
+
+
+def _gpu_foldin(g, mode, ptr, oidx, vals, method, sweeps=3):
+    import torch
+    from paper_1410_5209_amd import tf
+    nreq = len(ptr) - 1
+    d_idx = torch.from_numpy(np.ascontiguousarray(oidx)).cuda()
+    d_vals = torch.from_numpy(np.ascontiguousarray(vals)).cuda()
+    d_rows = torch.empty((nreq, g.K), dtype=torch.float64, device="cuda")
+    tf.tf_foldin(g.ctx, mode, ptr, d_idx, d_vals, method, sweeps, d_rows)
+    return d_rows.cpu().numpy()
+
+
+SIZES = [0, 1, 3, 17, 64, 65, 300, 1200]
+
+
+@pytest.mark.parametrize("mode,reg", [(0, 0), (1, 0), (2, 1)])
+@pytest.mark.parametrize("method", [0, 1])
+def test_foldin_parity_f64(mode, reg, method):
+    from paper_1410_5209_amd import tf
+    dims, K = [40, 30, 20], 6
+    note(f"foldin f64 mode={mode} reg={reg} method={method}")
+    idx, x, A = problem(31, dims, 3000, K, first_zero=False)
+    g, o = pair(dims, idx, x, A, K, 0.3, "f64", reg)
+    ptr, oidx, vals = _requests(dims, mode, SIZES, 5)
+    rows = _gpu_foldin(g, mode, ptr, oidx, vals, method)
+    for q in range(len(SIZES)):
+        sl = slice(ptr[q], ptr[q + 1])
+        want = o.foldin_full(mode, oidx[sl], vals[sl]) if method == tf.TF_FOLDIN_FULL else \
+            o.foldin_cdtf(mode, oidx[sl], vals[sl], 3)
+        if SIZES[q] == 0:
+            assert np.all(rows[q] == 0.0)
+        else:
+            assert rel_max(rows[q], want) < 1e-10, q
+    g.close()
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_foldin_k100_f32(method):
+    dims, K = [2000, 1500, 1000], 100
+    note(f"foldin f32 K=100 method={method}")
+    idx, x, A = problem(32, dims, 50000, K, first_zero=False)
+    g, o = pair(dims, idx, x, A, K, 1.0, "f32")
+    sizes = [1, 20, 375, 4300, 5000]
+    ptr, oidx, vals = _requests(dims, 0, sizes, 6)
+    rows = _gpu_foldin(g, 0, ptr, oidx, vals, method)
+    for q in range(len(sizes)):
+        sl = slice(ptr[q], ptr[q + 1])
+        want = o.foldin_full(0, oidx[sl], vals[sl]) if method == 0 else \
+            o.foldin_cdtf(0, oidx[sl], vals[sl], 3)
+        assert rel_max(rows[q], want) < 1e-4, q
+    g.close()
+
+
+def test_foldin_rejects_bad_index_and_large_k():
+    from paper_1410_5209_amd import tf
+    dims, K = [10, 10, 10], 4
+    note("foldin validation")
+    idx, x, A = problem(33, dims, 300, K, first_zero=False)
+    g, _ = pair(dims, idx, x, A, K, 0.3, "f64")
+    ptr, oidx, vals = _requests(dims, 0, [5, 5], 7)
+    oidx[7, 1] = 10
+    with pytest.raises(tf.TFError, match="entry 7"):
+        _gpu_foldin(g, 0, ptr, oidx, vals, 0)
+    g.close()
+    dims, K = [10, 10, 10], 130
+    idx, x, A = problem(34, dims, 300, K, first_zero=False)
+    g, o = pair(dims, idx, x, A, K, 0.3, "f64")
+    ptr, oidx, vals = _requests(dims, 0, [4], 8)
+    with pytest.raises(tf.TFError) as e:
+        _gpu_foldin(g, 0, ptr, oidx, vals, 0)
+    assert e.value.status == tf.TF_E_UNSUPPORTED
+    rows = _gpu_foldin(g, 0, ptr, oidx, vals, 1)          # CDTF has no K limit
+    assert rel_max(rows[0], o.foldin_cdtf(0, oidx, vals, 3)) < 1e-10
+    g.close()
+
+
+# ------------------------------------------------------------------ serving
+
+def _serve_setup(prec="f32", K=24):
+    dims = [3000, 2000, 1500]
+    idx, x, A = problem(35, dims, 60000, K, first_zero=False)
+    g, o = pair(dims, idx, x, A, K, 1.0, prec)
+    sizes = list(synth.zipf_ints(9, 500, 60, 1.1, 2000))
+    ptr, oidx, vals = _requests(dims, 0, sizes, 10)
+    return g, o, ptr, oidx, vals
+
+
+def _submit_all(tf, srv, ptr, oidx, vals, order):
+    keep, tickets = [], {}
+    for q in order:
+        sl = slice(ptr[q], ptr[q + 1])
+        oi = np.ascontiguousarray(oidx[sl])
+        va = np.ascontiguousarray(vals[sl])
+        keep.append((oi, va))
+        tickets[q] = tf.tf_serve_submit(srv, tf.make_request(oi, va))
+    return keep, tickets
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_serving_alone_and_mixed_are_bit_identical(method):
+    from paper_1410_5209_amd import tf
+    note(f"serving alone vs mix method={method}")
+    g, o, ptr, oidx, vals = _serve_setup()
+    nreq = len(ptr) - 1
+    batch_rows = _gpu_foldin(g, 0, ptr, oidx, vals, method)
+    srv = tf.tf_serve_open(g.ctx, tf.tf_serve_default_options(method=method, streams=3))
+    alone = np.empty((nreq, g.K))
+    for q in range(nreq):                      # one at a time
+        sl = slice(ptr[q], ptr[q + 1])
+        oi, va = np.ascontiguousarray(oidx[sl]), np.ascontiguousarray(vals[sl])
+        t = tf.tf_serve_submit(srv, tf.make_request(oi, va))
+        alone[q], st = tf.tf_serve_wait(srv, t, g.K)
+        assert st.batch_size >= 1
+    for order in (list(range(nreq)), list(reversed(range(nreq)))):   # bursts
+        keep, tickets = _submit_all(tf, srv, ptr, oidx, vals, order)
+        mixed = np.empty((nreq, g.K))
+        sizes = []
+        for q in order:
+            mixed[q], st = tf.tf_serve_wait(srv, tickets[q], g.K)
+            sizes.append(st.batch_size)
+        assert np.array_equal(mixed, alone)
+        assert max(sizes) > 1                  # the burst was batched
+    assert np.array_equal(alone, batch_rows)
+    rep = tf.tf_serve_report(srv)
+    assert rep.completed == 3 * nreq and rep.p99_us >= rep.p50_us > 0
+    tf.tf_serve_close(srv)
+    for q in range(nreq):
+        sl = slice(ptr[q], ptr[q + 1])
+        want = o.foldin_full(0, oidx[sl], vals[sl]) if method == 0 else \
+            o.foldin_cdtf(0, oidx[sl], vals[sl], 3)
+        assert rel_max(alone[q], want) < 1e-4
+    g.close()
+
+
+def test_serving_memory_admission_and_busy_queue():
+    from paper_1410_5209_amd import tf
+    note("serving admission")
+    g, o, ptr, oidx, vals = _serve_setup()
+    nreq = len(ptr) - 1
+    want = _gpu_foldin(g, 0, ptr, oidx, vals, 0)
+    biggest = int(np.max(np.diff(ptr)))
+    # a budget that holds one largest request per slot forces small batches
+    budget = 2 * (biggest * (2 * 4 + 8 + g.K * 4) + g.K * 8 + 4096)
+    srv = tf.tf_serve_open(g.ctx, tf.tf_serve_default_options(streams=2, mem_budget=budget,
+                                                              queue_cap=8))
+    keep, tickets, busy = [], {}, 0
+    for q in range(nreq):
+        sl = slice(ptr[q], ptr[q + 1])
+        oi, va = np.ascontiguousarray(oidx[sl]), np.ascontiguousarray(vals[sl])
+        keep.append((oi, va))
+        while True:
+            try:
+                tickets[q] = tf.tf_serve_submit(srv, tf.make_request(oi, va))
+                break
+            except tf.TFError as e:
+                assert e.status == tf.TF_E_BUSY
+                busy += 1
+    for q in range(nreq):
+        row, st = tf.tf_serve_wait(srv, tickets[q], g.K)
+        assert np.array_equal(row, want[q])
+    rep = tf.tf_serve_report(srv)
+    assert rep.busy_rejects == busy and rep.max_queue <= 8
+    assert rep.mean_batch < nreq
+    # a request larger than a slot's share is refused
+    big = 4 * biggest
+    oi = np.zeros((big, 2), dtype=np.int32)
+    va = np.ones(big)
+    with pytest.raises(tf.TFError) as e:
+        tf.tf_serve_submit(srv, tf.make_request(oi, va))
+    assert e.value.status == tf.TF_E_INVALID
+    tf.tf_serve_close(srv)
+    g.close()
+
+
+def test_serving_replay_poisson_and_close_with_work_in_flight():
+    from paper_1410_5209_amd import tf
+    note("serving replay")
+    g, o, ptr, oidx, vals = _serve_setup()
+    nreq = len(ptr) - 1
+    want = _gpu_foldin(g, 0, ptr, oidx, vals, 0)
+    srv = tf.tf_serve_open(g.ctx, tf.tf_serve_default_options(streams=2))
+    gaps = synth.exponential(11, 1, nreq, 2000.0)
+    arrival = np.cumsum(gaps)
+    keep = [(np.ascontiguousarray(oidx[ptr[q]:ptr[q + 1]]),
+             np.ascontiguousarray(vals[ptr[q]:ptr[q + 1]])) for q in range(nreq)]
+    reqs = [tf.make_request(oi, va) for oi, va in keep]
+    tickets = tf.tf_serve_replay(srv, arrival, reqs)
+    for q in range(nreq):
+        row, st = tf.tf_serve_wait(srv, int(tickets[q]), g.K)
+        assert np.array_equal(row, want[q]) and st.latency_us > 0
+    rep = tf.tf_serve_report(srv)
+    assert rep.completed == nreq and rep.solves_per_s > 0
+    # close while requests are queued / running: it drains and returns
+    for oi, va in keep:
+        tf.tf_serve_submit(srv, tf.make_request(oi, va))
+    tf.tf_serve_close(srv)
+    g.close()
