@@ -13,6 +13,9 @@ residual and Gram accumulation, FP64 Cholesky.  Inputs are generated on the
 host and resident in HBM before timing starts.
 
 Besides the JSON line fields the driver needs, it reports:
+  serving      fold-in of new mode-0 rows against the trained factors under
+               Poisson arrivals at 1k, 10k and 50k requests/s: p50/p99
+               latency and solves/s, full rank (C = K) and CDTF x 3
   roofline     achieved algorithmic GB/s of the row-accumulation kernel (HIP
                events around each launch on the library's stream) vs 8 TB/s;
                traffic = DRAM bytes per launch from rocprofv3 counters when the
@@ -88,6 +91,50 @@ def cpu_baseline(w, scale=4):
                       f"{dt:.2f} s; setup {t_setup:.1f} s untimed"}
 
 
+def serve_bench(m, w, rates, seconds, streams, max_batch):
+    """Fold-in serving against the trained, resident factors: Poisson arrivals
+    (exponential gaps) at each rate; request sizes Zipf(1.1) on [1, 5000];
+    other-mode indices uniform; values from the training ground truth.
+    Latency = submit -> row on the host.  The first 10% of each schedule warms
+    up and is not counted."""
+    import numpy as np
+
+    import synth
+    from paper_1410_5209_amd import tf
+
+    dims = [w.I] * w.N
+    out = []
+    for method, name in ((tf.TF_FOLDIN_FULL, "full-rank"), (tf.TF_FOLDIN_CDTF, "cdtf x3")):
+        srv = tf.tf_serve_open(m.ctx, tf.tf_serve_default_options(
+            method=method, sweeps=3, streams=streams, max_batch=max_batch,
+            mem_budget=2 << 30))
+        for rate in rates:
+            nreq = int(rate * seconds)
+            ptr, oidx, vals = synth.make_requests(dims, w.R, nreq, seed=synth.SEED_REQ + int(rate))
+            keep = [(np.ascontiguousarray(oidx[ptr[q]:ptr[q + 1]]),
+                     np.ascontiguousarray(vals[ptr[q]:ptr[q + 1]])) for q in range(nreq)]
+            reqs = [tf.make_request(a, b) for a, b in keep]
+            arrival = np.cumsum(synth.exponential(synth.SEED_REQ, 100 + int(rate), nreq, float(rate)))
+            nw = nreq // 10
+            t = tf.tf_serve_replay(srv, arrival[:nw], reqs[:nw])
+            for q in t:
+                tf.tf_serve_wait(srv, int(q), w.K)
+            tf.tf_serve_reset_stats(srv)
+            t = tf.tf_serve_replay(srv, arrival[nw:] - arrival[nw], reqs[nw:])
+            for q in t:
+                tf.tf_serve_wait(srv, int(q), w.K)
+            r = tf.tf_serve_report(srv)
+            out.append({"method": name, "rate_req_s": rate, "requests": int(r.completed),
+                        "p50_us": r.p50_us, "p90_us": r.p90_us, "p99_us": r.p99_us,
+                        "p999_us": r.p999_us, "max_us": r.max_us, "solves_per_s": r.solves_per_s,
+                        "mean_batch": r.mean_batch, "busy_rejects": int(r.busy_rejects),
+                        "mean_request_nnz": float(np.diff(ptr).mean())})
+            log(f"serve {name} {rate}/s: p50 {r.p50_us:.0f} us p99 {r.p99_us:.0f} us "
+                f"{r.solves_per_s:.0f} solves/s batch {r.mean_batch:.1f}")
+        tf.tf_serve_close(srv)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +144,10 @@ def main():
     ap.add_argument("--strategy", type=int, default=1)
     ap.add_argument("--lane-nnz", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the fold-in serving runs")
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--serve-max-batch", type=int, default=512)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -160,6 +211,10 @@ def main():
     bytes_per_launch = ks.alg_bytes / max(ks.launches, 1)
     achieved = (ks.alg_bytes / 1e9) / (ks.total_ms / 1000.0) if ks.total_ms > 0 else 0.0
     traffic = traffic_per_launch(args.workload)
+    serving = None
+    if not args.no_serve and w.N == 3 and w.K <= 128:
+        serving = serve_bench(m, w, [1000, 10000, 50000], args.serve_seconds, args.serve_streams,
+                              args.serve_max_batch)
     m.close()
     del m
     torch.cuda.empty_cache()
@@ -194,6 +249,7 @@ def main():
                      "alg_bytes_per_launch": bytes_per_launch,
                      "kernel_share_of_sweep": ks.total_ms / (dt * 1000.0)},
         "cpu_baseline": cpu,
+        "serving": serving,
         "loss_after": loss,
         "train_rmse_after": rmse,
     }
