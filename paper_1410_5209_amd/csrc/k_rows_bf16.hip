@@ -15,6 +15,7 @@ hipError_t launch_accum_bf16(int CP, int no, bool first, const AccumArgs &a, int
     TF_CP_CASE(accum_cp, 10, no, first, a, grid, st)
     TF_CP_CASE(accum_cp, 12, no, first, a, grid, st)
     TF_CP_CASE(accum_cp, 16, no, first, a, grid, st)
+    TF_CP_CASE(accum_wide, 32, no, first, a, grid, st)
     default: return hipErrorInvalidValue;
     }
 }
@@ -30,6 +31,7 @@ hipError_t launch_solve_bf16(int CP, const SolveArgs &a, hipStream_t st)
     TF_CP_CASE(solve_cp, 10, a, st)
     TF_CP_CASE(solve_cp, 12, a, st)
     TF_CP_CASE(solve_cp, 16, a, st)
+    TF_CP_CASE(solve_wide, 32, a, st)
     default: return hipErrorInvalidValue;
     }
 }
@@ -45,6 +47,7 @@ hipError_t launch_reduce_bf16(int CP, const int32_t *rows, const int32_t *ptr, i
     TF_CP_CASE(reduce_cp, 10, rows, ptr, nsplit, gpart, gram, st)
     TF_CP_CASE(reduce_cp, 12, rows, ptr, nsplit, gpart, gram, st)
     TF_CP_CASE(reduce_cp, 16, rows, ptr, nsplit, gpart, gram, st)
+    TF_CP_CASE(reduce_cp, 32, rows, ptr, nsplit, gpart, gram, st)
     default: return hipErrorInvalidValue;
     }
 }

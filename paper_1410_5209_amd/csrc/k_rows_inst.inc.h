@@ -3,6 +3,7 @@
 #pragma once
 
 #include "k_rows.inc.h"
+#include "k_rows_wide.inc.h"
 
 namespace tfk {
 
@@ -45,6 +46,39 @@ static hipError_t reduce_cp(const int32_t *rows, const int32_t *ptr, int nsplit,
 {
     hipLaunchKernelGGL((k_chunk_reduce<PREC, CP>), dim3(nsplit), dim3(256), 0, st, rows, ptr,
                        gpart, gram);
+    return hipGetLastError();
+}
+
+template <int PREC, int NO>
+static hipError_t accum_wide_no(bool first, const AccumArgs &a, int grid, hipStream_t st)
+{
+    if (first)
+        hipLaunchKernelGGL((k_accum_wide<PREC, NO, true>), dim3(grid), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_accum_wide<PREC, NO, false>), dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int PREC, int CP>
+static hipError_t accum_wide(int no, bool first, const AccumArgs &a, int grid, hipStream_t st)
+{
+    switch (no) {
+    case 1: return accum_wide_no<PREC, 1>(first, a, grid, st);
+    case 2: return accum_wide_no<PREC, 2>(first, a, grid, st);
+    case 3: return accum_wide_no<PREC, 3>(first, a, grid, st);
+    case 4: return accum_wide_no<PREC, 4>(first, a, grid, st);
+    case 5: return accum_wide_no<PREC, 5>(first, a, grid, st);
+    case 6: return accum_wide_no<PREC, 6>(first, a, grid, st);
+    case 7: return accum_wide_no<PREC, 7>(first, a, grid, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int PREC, int CP>
+static hipError_t solve_wide(const SolveArgs &a, hipStream_t st)
+{
+    const int grid = (int)((a.I + 3) / 4);
+    hipLaunchKernelGGL((k_solve_wide<PREC>), dim3(grid), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -82,7 +82,7 @@ void plan_rows(const int64_t *rowptr, int64_t I, int strategy, int lane_nnz, int
 int pick_cp(int C, int prec)
 {
     static const int f64[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
-    static const int f32[] = {1, 2, 4, 5, 8, 10, 12, 16};
+    static const int f32[] = {1, 2, 4, 5, 8, 10, 12, 16, 32};
     if (prec == P_F64) {
         for (int v : f64) if (v >= C) return v;
     } else {

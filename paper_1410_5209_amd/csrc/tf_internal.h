@@ -18,8 +18,9 @@ struct bf16 {
     uint16_t bits;
 };
 
-// Largest number of columns per split the register kernels are built for.
-constexpr int kMaxC = 16;
+// Largest number of columns per split: 16 for the register kernels (all
+// precisions), 32 for the wide kernels (FP32 and BF16 storage).
+constexpr int kMaxC = 32;
 constexpr int kMaxModes = 8;
 
 // Gram record of one row: upper triangle of B (c1 <= c2, row-major) then the

@@ -266,3 +266,53 @@ def test_library_init_draws_splitmix_factors():
         o.resync()
         assert rel_max(g.residual(), o.residual()) < 1e-14 or np.array_equal(g.residual(), x)
         g.close()
+
+
+# ------------------------------------------------------ 32-column splits
+
+@pytest.mark.parametrize("N,dims,nnz,dist", [
+    (3, [300, 250, 200], 30000, "uniform"),
+    (5, [60, 50, 40, 30, 20], 30000, "uniform"),
+    (5, [400, 300, 300, 200, 200], 40000, "zipf"),
+])
+def test_wide_split_parity_f32(N, dims, nnz, dist):
+    """C = 32 (one wavefront per row, 4x4 Gram blocks per lane), then a split of
+    8 columns whose pending 32 columns exceed that kernel's width."""
+    K = 40
+    note(f"wide f32 N={N} dims={dims} dist={dist}")
+    idx, x, A = problem(200 + N, dims, nnz, K, dist=dist,
+                        dedupe="drop" if dist == "zipf" else "distinct")
+    g, o = pair(dims, idx, x, A, K, 0.5, "f32", split_threshold=512, chunk_nnz=200)
+    for cols in (list(range(32)), list(range(32, 40)), list(range(4, 36))):
+        g.split(cols, 1)
+        o.split(cols, 1)
+        gl, gr = g.loss()
+        ol, orr = o.loss()
+        assert abs(gl - ol) <= 1e-4 * ol and abs(gr - orr) <= 1e-4 * orr, (cols[0], gl, ol)
+        for n in range(N):
+            assert rel_max(g.factor(n), o.get_factor(n)) < 1e-3, n
+    g.close()
+
+
+def test_wide_sweep_bf16_and_t_in_2():
+    dims, K = [200, 150, 100], 64
+    note("wide bf16 sweep")
+    idx, x, A = problem(210, dims, 20000, K)
+    g, o = pair(dims, idx, x, A, K, 0.5, "bf16")
+    g.sweep(32, 2)
+    o.sweep(32, 2)
+    gl, gr = g.loss()
+    ol, orr = o.loss()
+    assert abs(gr - orr) <= 5e-3 * orr and abs(gl - ol) <= 1e-2 * ol
+    g.close()
+
+
+def test_f64_rejects_wide_split():
+    from paper_1410_5209_amd import tf
+    dims, K = [20, 20, 20], 40
+    idx, x, A = problem(211, dims, 2000, K)
+    g, _ = pair(dims, idx, x, A, K, 0.5, "f64")
+    with pytest.raises(tf.TFError) as e:
+        g.split(list(range(20)), 1)
+    assert e.value.status == tf.TF_E_UNSUPPORTED
+    g.close()
