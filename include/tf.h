@@ -115,17 +115,19 @@ const char *tf_last_error(const tf_ctx *ctx);
  * columns, the last block shorter when C does not divide K.  For each block:
  * R-hat is formed, T_in inner iterations update every row of every mode by
  * eq. (SALS) (FP64 Cholesky, text after Theorem 1), and R is brought up to
- * date by eq. (SALS_R).  1 <= C <= min(K, 16); T_in >= 1.  Blocks until done.
+ * date by eq. (SALS_R).  1 <= C <= K with C <= 16 (FP64) or C <= 16 or
+ * 17..32 (FP32/BF16; run as 32 columns with zero padding); C = 0 uses the
+ * width chosen by tf_autotune.  T_in >= 1.  Blocks until done.
  * TF_E_NUMERIC: a pivot was not positive; the message names the mode and
- * row, and the context must be restored with tf_set_factor + tf_resync.
+ * row; that row keeps its previous value and the state stays consistent.
  * TF_E_STATE: factors were set without tf_resync.
  */
 tf_status tf_sweep(tf_ctx *ctx, int32_t C, int32_t T_in);
 
 /*
  * tf_split -- one block (split) of Algorithm 1 on the given columns:
- * h_cols host[ncols], distinct, in [0, K), 1 <= ncols <= 16.  Same
- * semantics and errors as one block of tf_sweep.
+ * h_cols host[ncols], distinct, in [0, K), with the same width limits as
+ * tf_sweep.  Same semantics and errors as one block of tf_sweep.
  */
 tf_status tf_split(tf_ctx *ctx, int32_t ncols, const int32_t *h_cols, int32_t T_in);
 
@@ -163,6 +165,29 @@ tf_status tf_get_residual(tf_ctx *ctx, double *h);
 
 /* Mode-n CSR: h_rowptr host[I_n + 1], h_perm host[nnz] (entry ids). */
 tf_status tf_get_csr(tf_ctx *ctx, int32_t n, int64_t *h_rowptr, int32_t *h_perm);
+
+/* ------------------------------------------------------------------ */
+/* Autotuning of the split width C and of the row tiles per mode.
+ * For each candidate C, times one trial split on the GPU: per mode a fused
+ * first pass (against a scratch copy of the residual) and, when T_in > 1, a
+ * plain pass; the estimated sweep time is ceil(K/C) times that plus slab
+ * packing.  Writes only scratch buffers: the model is unchanged.  With
+ * tune_tiles, then re-plans each mode over lanes-per-row targets {1,2,4,8}
+ * and chunk lengths {1024,4096,16384} (split threshold twice the chunk) for
+ * the chosen C and keeps the fastest plan.  Afterwards tf_sweep(ctx, 0, T_in)
+ * uses the chosen C.  Candidates must satisfy 1 <= C <= K and be runnable in
+ * the context's precision (C <= 16 in FP64, C <= 16 or C = 32 otherwise;
+ * C in 17..31 runs as 32 with zero padding). */
+typedef struct tf_tune_result {
+    int32_t best_C;
+    int32_t ncand;
+    int32_t cand_C[16];
+    double est_sweep_ms[16];
+    int32_t lane_nnz[8], split_threshold[8], chunk_nnz[8];   /* plan per mode */
+    double tune_ms;                                          /* wall time of the tuning */
+} tf_tune_result;
+tf_status tf_autotune(tf_ctx *ctx, int32_t T_in, const int32_t *h_cands, int32_t ncand,
+                      int32_t tune_tiles, tf_tune_result *out);
 
 /* ------------------------------------------------------------------ */
 /* Fold-in: new rows of one mode solved against the resident factors without

@@ -50,13 +50,16 @@ void plan_rows(const int64_t *rowptr, int64_t I, int strategy, int lane_nnz, int
     }
     auto heavier = [&](int32_t a, int32_t b) { return cnt(a) > cnt(b); };
 
-    // long rows first, cut into chunks of chunk_nnz entries
+    // long rows first, cut into chunks of chunk_nnz entries (larger for the
+    // longest rows, so that no row has more than kMaxChunksPerRow chunks and
+    // the fixed-order sum of its partials stays short)
     std::stable_sort(split.begin(), split.end(), heavier);
     for (int32_t row : split) {
         out->split_rows.push_back(row);
         out->split_chunk_ptr.push_back((int32_t)out->chunks.size());
-        for (int64_t b = rowptr[row]; b < rowptr[row + 1]; b += chunk_nnz) {
-            const int64_t e = std::min<int64_t>(b + chunk_nnz, rowptr[row + 1]);
+        const int64_t len = std::max<int64_t>(chunk_nnz, (cnt(row) + kMaxChunksPerRow - 1) / kMaxChunksPerRow);
+        for (int64_t b = rowptr[row]; b < rowptr[row + 1]; b += len) {
+            const int64_t e = std::min<int64_t>(b + len, rowptr[row + 1]);
             const int32_t slot = (int32_t)out->chunks.size();
             out->tasks.push_back(Task{64, slot, 1, 1});
             out->chunks.push_back(Chunk{row, (int32_t)b, (int32_t)e, slot});

@@ -1,5 +1,6 @@
 // C ABI of the SALS / CDTF GPU path: context construction, the split driver
 // of Algorithm 1 (arXiv:1410.5209), loss, prediction and state access.
+#include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstdarg>
@@ -94,19 +95,21 @@ int key_bits_for(int64_t I)
 // Ensure the Gram buffers hold records of compute width CP.
 tf_status ensure_gram(tf_ctx *c, int CP)
 {
-    if (CP <= c->slab_cp && c->gram) return TF_OK;
-    dfree(c->gram);
-    dfree(c->gpart);
-    c->gram = c->gpart = nullptr;
     int64_t maxI = 0, maxch = 1;
     for (int n = 0; n < c->N; ++n) {
         maxI = std::max<int64_t>(maxI, c->m[n].I);
         maxch = std::max<int64_t>(maxch, c->m[n].nchunks);
     }
-    const size_t rec = (size_t)gram_stride(CP) * ta_size(c->prec);
+    if (CP <= c->slab_cp && c->gram && maxch <= c->gpart_chunks) return TF_OK;
+    const int cp = std::max(CP, c->slab_cp);
+    dfree(c->gram);
+    dfree(c->gpart);
+    c->gram = c->gpart = nullptr;
+    const size_t rec = (size_t)gram_stride(cp) * ta_size(c->prec);
     HIPCHK(c, hipMalloc(&c->gram, (size_t)maxI * rec));
     HIPCHK(c, hipMalloc(&c->gpart, (size_t)maxch * rec));
-    c->slab_cp = CP;
+    c->slab_cp = cp;
+    c->gpart_chunks = maxch;
     return TF_OK;
 }
 
@@ -393,6 +396,31 @@ tf_status upload_vec(tf_ctx *c, T **dst, const std::vector<T> &v)
     return TF_OK;
 }
 
+// Plan mode n's rows with the given tile parameters and upload the plan.
+tf_status apply_plan(tf_ctx *c, int n, int lane_nnz, int split_threshold, int chunk_nnz)
+{
+    auto &md = c->m[n];
+    HostPlan plan;
+    plan_rows(md.h_rowptr.data(), md.I, c->opt.strategy, lane_nnz, split_threshold, chunk_nnz, &plan);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    dfree(md.tasks); dfree(md.items); dfree(md.chunks); dfree(md.split_rows); dfree(md.split_chunk_ptr);
+    md.tasks = nullptr; md.items = nullptr; md.chunks = nullptr;
+    md.split_rows = nullptr; md.split_chunk_ptr = nullptr;
+    tf_status s;
+    if ((s = upload_vec(c, &md.tasks, plan.tasks)) != TF_OK) return s;
+    if ((s = upload_vec(c, &md.items, plan.items)) != TF_OK) return s;
+    if ((s = upload_vec(c, &md.chunks, plan.chunks)) != TF_OK) return s;
+    if ((s = upload_vec(c, &md.split_rows, plan.split_rows)) != TF_OK) return s;
+    if ((s = upload_vec(c, &md.split_chunk_ptr, plan.split_chunk_ptr)) != TF_OK) return s;
+    md.ntasks = (int32_t)plan.tasks.size();
+    md.nchunks = (int32_t)plan.chunks.size();
+    md.nsplit = (int32_t)plan.split_rows.size();
+    md.lane_nnz = lane_nnz;
+    md.split_threshold = split_threshold;
+    md.chunk_nnz = chunk_nnz;
+    return TF_OK;
+}
+
 tf_status build_state(tf_ctx *c, const int32_t *d_idx, const double *d_vals)
 {
     const int N = c->N;
@@ -450,18 +478,8 @@ tf_status build_state(tf_ctx *c, const int32_t *d_idx, const double *d_vals)
                                  hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
         md.h_rowptr.assign(rp32.begin(), rp32.end());
-        HostPlan plan;
-        plan_rows(md.h_rowptr.data(), md.I, c->opt.strategy, c->opt.lane_nnz,
-                  c->opt.split_threshold, c->opt.chunk_nnz, &plan);
-        tf_status s;
-        if ((s = upload_vec(c, &md.tasks, plan.tasks)) != TF_OK) return s;
-        if ((s = upload_vec(c, &md.items, plan.items)) != TF_OK) return s;
-        if ((s = upload_vec(c, &md.chunks, plan.chunks)) != TF_OK) return s;
-        if ((s = upload_vec(c, &md.split_rows, plan.split_rows)) != TF_OK) return s;
-        if ((s = upload_vec(c, &md.split_chunk_ptr, plan.split_chunk_ptr)) != TF_OK) return s;
-        md.ntasks = (int32_t)plan.tasks.size();
-        md.nchunks = (int32_t)plan.chunks.size();
-        md.nsplit = (int32_t)plan.split_rows.size();
+        tf_status s = apply_plan(c, n, c->opt.lane_nnz, c->opt.split_threshold, c->opt.chunk_nnz);
+        if (s != TF_OK) return s;
     }
 
     // factors (Section 3.1: A^(1) = 0, the others random, so that R = X)
@@ -602,6 +620,10 @@ tf_status tf_split(tf_ctx *ctx, int32_t ncols, const int32_t *h_cols, int32_t T_
 tf_status tf_sweep(tf_ctx *ctx, int32_t C, int32_t T_in)
 {
     if (!ctx) return TF_E_INVALID;
+    if (C == 0) {
+        if (ctx->tuned_C == 0) return CTX_FAIL(ctx, TF_E_STATE, "C = 0 needs tf_autotune first");
+        C = ctx->tuned_C;
+    }
     if (C < 1 || C > ctx->K || T_in < 1) return CTX_FAIL(ctx, TF_E_INVALID, "need 1 <= C <= K, T_in >= 1");
     if (C > kMaxC) return CTX_FAIL(ctx, TF_E_UNSUPPORTED, "C = %d exceeds %d", C, kMaxC);
     tf_status s = check_ready(ctx);
@@ -613,6 +635,147 @@ tf_status tf_sweep(tf_ctx *ctx, int32_t C, int32_t T_in)
     }
     ctx->kstats.sweeps += 1;
     return check_bad(ctx);
+}
+
+namespace {
+
+// One timed pass on mode n (accumulation, chunk sums, solve) reading the
+// residual from `rhat`; returns milliseconds.
+tf_status time_pass(tf_ctx *c, int n, int CP, int npend, bool first, void *rhat, double *ms)
+{
+    auto &md = c->m[n];
+    AccumArgs a;
+    fill_accum_args(c, n, first ? npend : 0, &a);
+    a.rhat = rhat;
+    hipEvent_t e0 = take_event(c), e1 = take_event(c);
+    if (!e0 || !e1) return CTX_FAIL(c, TF_E_DEVICE, "event creation failed");
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+    const int grid = (md.ntasks + 3) / 4;
+    if (grid > 0) HIPCHK(c, launch_accum(c->prec, CP, c->N - 1, first, a, grid, c->stream));
+    if (md.nsplit > 0)
+        HIPCHK(c, launch_chunk_reduce(c->prec, CP, md.split_rows, md.split_chunk_ptr, md.nsplit,
+                                      c->gpart, c->gram, c->stream));
+    SolveArgs sa;
+    sa.rowptr = md.rowptr; sa.I = md.I; sa.gram = c->gram; sa.W = md.Z; sa.ld = c->ld;
+    sa.lambda = c->lambda; sa.reg_mode = c->opt.reg_mode; sa.bad = c->d_bad + n;
+    HIPCHK(c, launch_solve(c->prec, CP, sa, c->stream));
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(e1));
+    float f = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&f, e0, e1));
+    c->ev_free.push_back(e0);
+    c->ev_free.push_back(e1);
+    *ms = f;
+    return TF_OK;
+}
+
+// Set up a steady-state trial split of width C: current columns order[0..C),
+// pending columns the last C of the order, slabs packed for both.
+tf_status trial_slabs(tf_ctx *c, int C, int *CP_out, int *npend_out)
+{
+    const int CP = pick_cp(C, c->prec);
+    if (CP < 0) return CTX_FAIL(c, TF_E_UNSUPPORTED, "C = %d not runnable in this precision", C);
+    tf_status s = ensure_gram(c, CP);
+    if (s != TF_OK) return s;
+    const int npend = C;
+    std::vector<int32_t> cols(c->order.begin(), c->order.begin() + C);
+    const auto saved = c->pend;
+    c->pend.assign(c->order.end() - C, c->order.end());
+    slab_geometry(c, CP);
+    s = upload_cols(c, cols.data(), C);
+    c->pend = saved;
+    if (s != TF_OK) return s;
+    if ((s = pack_all(c, c->d_cols, C, c->d_cols + c->K, npend)) != TF_OK) return s;
+    *CP_out = CP;
+    *npend_out = npend;
+    return TF_OK;
+}
+
+}  // namespace
+
+extern "C" tf_status tf_autotune(tf_ctx *ctx, int32_t T_in, const int32_t *h_cands, int32_t ncand,
+                                 int32_t tune_tiles, tf_tune_result *out)
+{
+    if (!ctx) return TF_E_INVALID;
+    if (!h_cands || ncand < 1 || ncand > 16 || T_in < 1 || !out)
+        return CTX_FAIL(ctx, TF_E_INVALID, "need 1..16 candidates, T_in >= 1, an output");
+    for (int q = 0; q < ncand; ++q)
+        if (h_cands[q] < 1 || h_cands[q] > ctx->K || pick_cp(h_cands[q], ctx->prec) < 0)
+            return CTX_FAIL(ctx, TF_E_INVALID, "candidate C = %d not runnable", h_cands[q]);
+    tf_status s = check_ready(ctx);
+    if (s != TF_OK) return s;
+    const auto t_start = std::chrono::steady_clock::now();
+    std::memset(out, 0, sizeof *out);
+    void *scratch = nullptr;
+    HIPCHK(ctx, hipMalloc(&scratch, (size_t)ctx->nnz * tr_size(ctx->prec)));
+    struct Free { void *p; ~Free() { dfree(p); } } guard{scratch};
+    if ((s = reset_bad(ctx)) != TF_OK) return s;
+
+    double best = 1e300;
+    int bestC = h_cands[0];
+    for (int q = 0; q < ncand; ++q) {
+        const int C = h_cands[q];
+        int CP = 0, npend = 0;
+        if ((s = trial_slabs(ctx, C, &CP, &npend)) != TF_OK) return s;
+        double split_ms = 0.0;
+        for (int n = 0; n < ctx->N; ++n) {
+            HIPCHK(ctx, hipMemcpyAsync(scratch, ctx->m[n].rhat, (size_t)ctx->nnz * tr_size(ctx->prec),
+                                       hipMemcpyDeviceToDevice, ctx->stream));
+            double t1 = 0.0, t2 = 0.0;
+            if ((s = time_pass(ctx, n, CP, npend, true, scratch, &t1)) != TF_OK) return s;
+            if (T_in > 1 && (s = time_pass(ctx, n, CP, npend, false, scratch, &t2)) != TF_OK) return s;
+            split_ms += t1 + (T_in - 1) * t2;
+        }
+        // slab packing and write-back: time one packing of all modes, count it twice
+        hipEvent_t e0 = take_event(ctx), e1 = take_event(ctx);
+        HIPCHK(ctx, hipEventRecord(e0, ctx->stream));
+        if ((s = pack_all(ctx, ctx->d_cols, C, ctx->d_cols + ctx->K, npend)) != TF_OK) return s;
+        HIPCHK(ctx, hipEventRecord(e1, ctx->stream));
+        HIPCHK(ctx, hipEventSynchronize(e1));
+        float pk = 0.f;
+        HIPCHK(ctx, hipEventElapsedTime(&pk, e0, e1));
+        ctx->ev_free.push_back(e0);
+        ctx->ev_free.push_back(e1);
+        const double est = (double)((ctx->K + C - 1) / C) * (split_ms + 2.0 * pk);
+        out->cand_C[q] = C;
+        out->est_sweep_ms[q] = est;
+        if (est < best) { best = est; bestC = C; }
+    }
+    out->ncand = ncand;
+    out->best_C = bestC;
+    ctx->tuned_C = bestC;
+
+    if (tune_tiles) {
+        static const int lanes[] = {1, 2, 4, 8};
+        static const int chunks[] = {1024, 4096, 16384};
+        int CP = 0, npend = 0;
+        for (int n = 0; n < ctx->N; ++n) {
+            double tbest = 1e300;
+            int bl = ctx->m[n].lane_nnz, bs = ctx->m[n].split_threshold, bc = ctx->m[n].chunk_nnz;
+            for (int lane : lanes)
+                for (int ch : chunks) {
+                    if ((s = apply_plan(ctx, n, lane, 2 * ch, ch)) != TF_OK) return s;
+                    if ((s = trial_slabs(ctx, bestC, &CP, &npend)) != TF_OK) return s;
+                    HIPCHK(ctx, hipMemcpyAsync(scratch, ctx->m[n].rhat, (size_t)ctx->nnz * tr_size(ctx->prec),
+                                               hipMemcpyDeviceToDevice, ctx->stream));
+                    double t1 = 0.0, t2 = 0.0;
+                    if ((s = time_pass(ctx, n, CP, npend, true, scratch, &t1)) != TF_OK) return s;
+                    if (T_in > 1 && (s = time_pass(ctx, n, CP, npend, false, scratch, &t2)) != TF_OK) return s;
+                    const double t = t1 + (T_in - 1) * t2;
+                    if (t < tbest) { tbest = t; bl = lane; bs = 2 * ch; bc = ch; }
+                }
+            if ((s = apply_plan(ctx, n, bl, bs, bc)) != TF_OK) return s;
+        }
+        if ((s = ensure_gram(ctx, pick_cp(bestC, ctx->prec))) != TF_OK) return s;
+    }
+    for (int n = 0; n < ctx->N && n < 8; ++n) {
+        out->lane_nnz[n] = ctx->m[n].lane_nnz;
+        out->split_threshold[n] = ctx->m[n].split_threshold;
+        out->chunk_nnz[n] = ctx->m[n].chunk_nnz;
+    }
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    out->tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    return TF_OK;
 }
 
 tf_status tf_set_col_order(tf_ctx *ctx, const int32_t *h_order)

@@ -50,6 +50,8 @@ struct Chunk {
     int32_t slot;
 };
 
+constexpr int64_t kMaxChunksPerRow = 1024;
+
 struct HostPlan {
     std::vector<Task> tasks;
     std::vector<int32_t> items;
@@ -197,11 +199,14 @@ struct tf_ctx {
         int32_t *split_chunk_ptr = nullptr;
         int32_t nsplit = 0;
         std::vector<int64_t> h_rowptr;
+        int32_t lane_nnz = 0, split_threshold = 0, chunk_nnz = 0;   // plan in use
     } m[tfk::kMaxModes];
 
     int64_t ld = 0;           // slab row stride (elements, 128-byte multiple)
     int64_t sw = 0;           // slab segment width (elements)
-    int slab_cp = 0;          // compute width the slabs are sized for
+    int slab_cp = 0;          // compute width the Gram buffers are sized for
+    int64_t gpart_chunks = 0; // chunk records the partial buffer holds
+    int tuned_C = 0;          // chosen by tf_autotune (0: none)
     void *gram = nullptr;     // max_I x gram_stride(slab_cp) (TA)
     void *gpart = nullptr;    // max_chunks x gram_stride(slab_cp) (TA)
     int32_t *d_cols = nullptr;  // device copy of split columns + pending columns

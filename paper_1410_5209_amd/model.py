@@ -90,6 +90,9 @@ class SparseCP:
     def csr(self, n):
         return tf.tf_get_csr(self.ctx, n, self.dims[n], self.nnz)
 
+    def autotune(self, T_in, cands, tune_tiles=True):
+        return tf.tf_autotune(self.ctx, T_in, cands, tune_tiles)
+
     def profile(self, enable=True):
         tf.tf_profile(self.ctx, enable)
 

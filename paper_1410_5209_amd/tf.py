@@ -70,6 +70,13 @@ class tf_serve_stats(ctypes.Structure):
 TF_FOLDIN_FULL, TF_FOLDIN_CDTF = 0, 1
 
 
+class tf_tune_result(ctypes.Structure):
+    _fields_ = [("best_C", ctypes.c_int32), ("ncand", ctypes.c_int32),
+                ("cand_C", ctypes.c_int32 * 16), ("est_sweep_ms", ctypes.c_double * 16),
+                ("lane_nnz", ctypes.c_int32 * 8), ("split_threshold", ctypes.c_int32 * 8),
+                ("chunk_nnz", ctypes.c_int32 * 8), ("tune_ms", ctypes.c_double)]
+
+
 class TFError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"tf status {status}: {msg}")
@@ -109,6 +116,7 @@ def lib():
         L.tf_profile_read.argtypes = [P, ctypes.POINTER(tf_kstats)]
         L.tf_plan_rows.argtypes = [P, i64, i32, i32, i32, i32, ctypes.POINTER(tf_plan_summary)]
         L.tf_foldin.argtypes = [P, i32, i32, P, P, P, i32, i32, P]
+        L.tf_autotune.argtypes = [P, i32, P, i32, i32, ctypes.POINTER(tf_tune_result)]
         L.tf_serve_default_options.argtypes = [ctypes.POINTER(tf_serve_opts)]
         L.tf_serve_default_options.restype = None
         L.tf_serve_open.argtypes = [P, ctypes.POINTER(tf_serve_opts), ctypes.POINTER(P)]
@@ -124,7 +132,7 @@ def lib():
                      "tf_get_residual", "tf_get_csr", "tf_profile", "tf_profile_read",
                      "tf_plan_rows", "tf_foldin", "tf_serve_open", "tf_serve_submit",
                      "tf_serve_wait", "tf_serve_replay", "tf_serve_report",
-                     "tf_serve_reset_stats"):
+                     "tf_serve_reset_stats", "tf_autotune"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -251,6 +259,14 @@ def tf_plan_rows(rowptr, strategy=TF_STRATEGY_SKEW, lane_nnz=2, split_threshold=
                                     int(lane_nnz), int(split_threshold), int(chunk_nnz),
                                     ctypes.byref(s)))
     return s
+
+
+def tf_autotune(ctx, T_in, cands, tune_tiles=True) -> tf_tune_result:
+    cands = np.ascontiguousarray(cands, dtype=np.int32)
+    r = tf_tune_result()
+    _check(ctx, lib().tf_autotune(ctx, int(T_in), _np(cands), int(cands.shape[0]),
+                                  1 if tune_tiles else 0, ctypes.byref(r)))
+    return r
 
 
 def tf_foldin(ctx, mode, h_req_ptr, d_idx, d_vals, method, sweeps, d_rows):

@@ -316,3 +316,27 @@ def test_f64_rejects_wide_split():
         g.split(list(range(20)), 1)
     assert e.value.status == tf.TF_E_UNSUPPORTED
     g.close()
+
+
+def test_autotune_leaves_model_unchanged_and_sweeps_with_chosen_width():
+    dims, K = [400, 300, 200], 40
+    note("autotune")
+    idx, x, A = problem(220, dims, 40000, K, dist="zipf", dedupe="drop")
+    g, o = pair(dims, idx, x, A, K, 0.5, "f32", split_threshold=512, chunk_nnz=128)
+    g.split(list(range(8)), 1)
+    o.split(list(range(8)), 1)
+    F0, r0 = g.factors(), g.residual()
+    res = g.autotune(1, [4, 8, 16, 32], tune_tiles=True)
+    assert res.best_C in (4, 8, 16, 32) and res.ncand == 4
+    assert all(res.est_sweep_ms[q] > 0 for q in range(4))
+    assert all(res.lane_nnz[n] in (1, 2, 4, 8) for n in range(3))
+    for n in range(3):
+        assert np.array_equal(g.factor(n), F0[n])
+    assert np.array_equal(g.residual(), r0)
+    g.sweep(0, 1)
+    order = np.arange(K)
+    o.sweep(res.best_C, 1, order)
+    gl, gr = g.loss()
+    ol, orr = o.loss()
+    assert abs(gl - ol) <= 1e-4 * ol and abs(gr - orr) <= 1e-4 * orr
+    g.close()
