@@ -66,13 +66,13 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, scale=4):
+def cpu_baseline(w, scale=4, C=None):
     """The oracle as it stands, on one split of the same recipe at 1/scale size
     (mode lengths and entries both divided by `scale`, so every row keeps the
     full workload's mean length; K, C, T_in, lambda unchanged)."""
     import synth
     from oracle import oracle as orc
-    r = w.replica(w.I // scale, w.nnz // scale)
+    r = w.replica(w.I // scale, w.nnz // scale, C=C or w.C)
     idx, x = synth.make_tensor(r)[:2]
     t0 = time.perf_counter()
     o = orc.Oracle([r.I] * r.N, idx, x, r.K, r.lam)
@@ -144,6 +144,11 @@ def main():
     ap.add_argument("--strategy", type=int, default=1)
     ap.add_argument("--lane-nnz", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", default=None,
+                    help="comma-separated candidate C values; the sweep then uses the tuned C "
+                         "(default for the 5-way Zipf workload: 8,16,32)")
+    ap.add_argument("--cpu-scale", type=int, default=0,
+                    help="oracle sample at 1/scale size (default 4; 40 for the 5-way workload)")
     ap.add_argument("--no-serve", action="store_true", help="skip the fold-in serving runs")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--serve-streams", type=int, default=4)
@@ -186,8 +191,20 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    cands = args.autotune or ("8,16,32" if w.name == "sals-5way-zipf-fp32" else None)
+    C = w.C
+    tune = None
+    if cands:
+        r = m.autotune(w.T_in, [int(c) for c in cands.split(",")], tune_tiles=True)
+        C = r.best_C
+        tune = {"candidates": [int(c) for c in cands.split(",")],
+                "est_sweep_ms": [r.est_sweep_ms[q] for q in range(r.ncand)], "chosen_C": C,
+                "lane_nnz": list(r.lane_nnz)[:w.N], "chunk_nnz": list(r.chunk_nnz)[:w.N],
+                "tune_ms": r.tune_ms}
+        log(f"autotune: C={C} ({r.tune_ms:.0f} ms)")
+
     for s in range(args.warmup):
-        m.sweep(w.C, w.T_in)
+        m.sweep(C, w.T_in)
         log(f"warmup sweep {s} done")
     torch.cuda.synchronize()
 
@@ -195,7 +212,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
-        m.sweep(w.C, w.T_in)
+        m.sweep(C, w.T_in)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ks = m.profile_read()
@@ -223,7 +240,8 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the oracle on one split")
         del idx, x
-        cpu = cpu_baseline(w)
+        scale = args.cpu_scale or (40 if w.N == 5 else 4)
+        cpu = cpu_baseline(w, scale, C)
 
     out = {
         "metric": METRIC,
@@ -238,7 +256,8 @@ def main():
         "vs_baseline": None,
         "dtype": {"f64": "f64", "f32": "f32", "bf16": "bf16-storage/f32"}[w.prec],
         "data": "synthetic",
-        "config": {"workload": w.name, "N": w.N, "I": w.I, "nnz": nnz, "K": w.K, "C": w.C,
+        "config": {"workload": w.name, "N": w.N, "I": w.I, "nnz": nnz, "K": w.K, "C": C,
+                   "autotune": tune,
                    "T_in": w.T_in, "lambda": w.lam, "precision": w.prec,
                    "strategy": "skew" if args.strategy == 1 else "plain",
                    "parallelism": "single-gpu"},

@@ -1,6 +1,5 @@
-// Residual evaluation on the mode copies, the loss of eq. (TF), the
-// stand-alone residual update of a split boundary, and prediction
-// (arXiv:1410.5209: eq. (TF), eq. (SALS_R), R-hat of Algorithm 1).
+// Residual evaluation on the mode copies, the loss of eq. (TF), and
+// prediction (arXiv:1410.5209: eq. (TF), eq. (SALS_R)).
 //
 // The mode copies hold R-hat of the last split (x minus every column outside
 // that split), so the true residual is r = rhat - sum_{c in last split}
@@ -88,49 +87,6 @@ hipError_t launch_eval_residual(int prec, const EvalArgs &a, int grid, hipStream
     if (prec == P_F64) hipLaunchKernelGGL(k_eval_resid<P_F64>, dim3(grid), dim3(256), 0, st, a);
     else if (prec == P_F32) hipLaunchKernelGGL(k_eval_resid<P_F32>, dim3(grid), dim3(256), 0, st, a);
     else hipLaunchKernelGGL(k_eval_resid<P_BF16>, dim3(grid), dim3(256), 0, st, a);
-    return hipGetLastError();
-}
-
-// Split boundary on one mode copy, not fused into a row pass (used when the
-// previous split had more columns than the current row kernel carries):
-// rhat <- (rhat - sum_{pending c} prod_n P) + sum_{current c} prod_n S,
-// every factor value taken at the start of the split.
-template <int PREC>
-__global__ __launch_bounds__(256) void k_sync(AccumArgs a, int npend, int ncur)
-{
-    using TS = typename Types<PREC>::TS;
-    using TR = typename Types<PREC>::TR;
-    using TA = typename Types<PREC>::TA;
-    const int lane = threadIdx.x & 63;
-    const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (t >= a.ntasks) return;
-    const Slot s = task_slot(a.tasks, a.items, a.chunks, a.rowptr, t, lane);
-    TR *rh = reinterpret_cast<TR *>(a.rhat);
-    const TS *Pown = reinterpret_cast<const TS *>(a.Pown) + (int64_t)s.row * a.ld;
-    const TS *Sown = reinterpret_cast<const TS *>(a.Sown) + (int64_t)s.row * a.ld;
-    for (int64_t j = s.beg + s.sub; j < s.end; j += s.G) {
-        TA dr = TA(0), ds = TA(0);
-        for (int c = 0; c < npend; ++c) {
-            TA prod = (TA)load_f64(Pown + c);
-            for (int l = 0; l < a.no; ++l)
-                prod *= (TA)load_f64(reinterpret_cast<const TS *>(a.P[l]) + (int64_t)a.oidx[l][j] * a.ld + c);
-            dr += prod;
-        }
-        for (int c = 0; c < ncur; ++c) {
-            TA prod = (TA)load_f64(Sown + c);
-            for (int l = 0; l < a.no; ++l)
-                prod *= (TA)load_f64(reinterpret_cast<const TS *>(a.S[l]) + (int64_t)a.oidx[l][j] * a.ld + c);
-            ds += prod;
-        }
-        rh[j] = (TR)(((TA)rh[j] - dr) + ds);
-    }
-}
-
-hipError_t sync_copy(int prec, const AccumArgs &a, int npend, int ncur, int grid, hipStream_t st)
-{
-    if (prec == P_F64) hipLaunchKernelGGL(k_sync<P_F64>, dim3(grid), dim3(256), 0, st, a, npend, ncur);
-    else if (prec == P_F32) hipLaunchKernelGGL(k_sync<P_F32>, dim3(grid), dim3(256), 0, st, a, npend, ncur);
-    else hipLaunchKernelGGL(k_sync<P_BF16>, dim3(grid), dim3(256), 0, st, a, npend, ncur);
     return hipGetLastError();
 }
 

@@ -305,8 +305,10 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs a)
     for (int c = 0; c < CP; ++c) o[c] = store_cast<TS>(y[c]);
 }
 
-// Sum of the chunk partials of each split row, in chunk order, into the
-// row's Gram record.
+// Sum of the chunk partials of each split row into the row's Gram record.
+// Every thread owns some entries of the record; chunk c goes to partial sum
+// c mod 8, and the eight partials are added in a fixed tree, so the result
+// does not depend on scheduling (and eight loads are in flight per thread).
 template <int PREC, int CP>
 __global__ __launch_bounds__(256) void k_chunk_reduce(const int32_t *split_rows,
                                                       const int32_t *ptr, const void *gpart,
@@ -319,11 +321,18 @@ __global__ __launch_bounds__(256) void k_chunk_reduce(const int32_t *split_rows,
     const int row = split_rows[b];
     const TA *gp = reinterpret_cast<const TA *>(gpart);
     TA *gr = reinterpret_cast<TA *>(gram) + (int64_t)row * NEP;
+    const int c0 = ptr[b], c1 = ptr[b + 1];
     for (int e = threadIdx.x; e < NEP; e += blockDim.x) {
-        double s = 0.0;
-        if (e < NE)
-            for (int c = ptr[b]; c < ptr[b + 1]; ++c) s += (double)gp[(int64_t)c * NEP + e];
-        gr[e] = (TA)s;
+        double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (e < NE) {
+            int c = c0;
+            for (; c + 8 <= c1; c += 8) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s[u] += (double)gp[(int64_t)(c + u) * NEP + e];
+            }
+            for (int u = 0; c < c1; ++c, ++u) s[u] += (double)gp[(int64_t)c * NEP + e];
+        }
+        gr[e] = (TA)(((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])));
     }
 }
 

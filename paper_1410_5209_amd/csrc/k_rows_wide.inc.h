@@ -99,16 +99,31 @@ __global__ __launch_bounds__(256) void k_accum_wide(AccumArgs a)
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[u][v] = 0.f;
         }
+        // indices and residual of the next step are requested while the
+        // current step's factor rows are gathered and folded in
+        int32_t nx[NO];
+        TR nr = TR(0);
+        if (beg + e < end) {
+#pragma unroll
+            for (int l = 0; l < NO; ++l) nx[l] = a.oidx[l][beg + e];
+            nr = rhat[beg + e];
+        }
         for (int64_t s0 = beg; s0 < end; s0 += 8) {
             const int64_t j = s0 + e;
             const bool valid = j < end;
+            int32_t ii[NO];
+#pragma unroll
+            for (int l = 0; l < NO; ++l) ii[l] = nx[l];
+            const TR rcur = nr;
+            if (j + 8 < end) {
+#pragma unroll
+                for (int l = 0; l < NO; ++l) nx[l] = a.oidx[l][j + 8];
+                nr = rhat[j + 8];
+            }
             float p[4] = {0.f, 0.f, 0.f, 0.f};
             float r = 0.f, dr = 0.f, ds = 0.f;   // this lane's four columns of the update
             if (valid) {
-                int32_t ii[NO];
-#pragma unroll
-                for (int l = 0; l < NO; ++l) ii[l] = a.oidx[l][j];
-                r = (float)rhat[j];
+                r = (float)rcur;
                 float w[NO][4];
 #pragma unroll
                 for (int l = 0; l < NO; ++l)

@@ -220,12 +220,17 @@ tf_status upload_cols(tf_ctx *c, const int32_t *cols, int ncols)
 // One split of Algorithm 1 on columns cols[0..ncols).
 tf_status run_split(tf_ctx *c, const int32_t *cols, int ncols, int T_in)
 {
-    const int CP = pick_cp(ncols, c->prec);
+    // the kernels run at a width covering both this split's and the pending
+    // columns, so the residual update stays fused into the first pass (the
+    // padded columns are zero in every slab segment, which leaves the real
+    // columns' solution unchanged and the padded ones at zero)
+    int CP = pick_cp(std::max<int>(ncols, (int)c->pend.size()), c->prec);
+    if (CP < 0) CP = pick_cp(ncols, c->prec);
     if (CP < 0) return CTX_FAIL(c, TF_E_UNSUPPORTED, "C = %d exceeds %d columns per split", ncols, kMaxC);
     tf_status s = ensure_gram(c, CP);
     if (s != TF_OK) return s;
     const int npend = (int)c->pend.size();
-    const bool fuse = npend <= CP;
+    if (npend > CP) return CTX_FAIL(c, TF_E_UNSUPPORTED, "pending columns exceed the kernel width");
     slab_geometry(c, std::max(CP, npend));
     if ((s = upload_cols(c, cols, ncols)) != TF_OK) return s;
     const int32_t *d_cur = c->d_cols;
@@ -235,19 +240,10 @@ tf_status run_split(tf_ctx *c, const int32_t *cols, int ncols, int T_in)
     // the split's columns, P the previous split's columns (final values)
     if ((s = pack_all(c, d_cur, ncols, d_pend, npend)) != TF_OK) return s;
 
-    if (!fuse) {  // bring every copy to R-hat of this split before the passes
-        for (int n = 0; n < c->N; ++n) {
-            AccumArgs a;
-            fill_accum_args(c, n, npend, &a);
-            const int grid = (c->m[n].ntasks + 3) / 4;
-            if (grid > 0) HIPCHK(c, sync_copy(c->prec, a, npend, ncols, grid, c->stream));
-        }
-    }
-
     for (int it = 0; it < T_in; ++it) {
         for (int n = 0; n < c->N; ++n) {
             auto &md = c->m[n];
-            const bool first = fuse && it == 0;
+            const bool first = it == 0;
             AccumArgs a;
             fill_accum_args(c, n, first ? npend : 0, &a);
             const int grid = (md.ntasks + 3) / 4;

@@ -156,8 +156,6 @@ struct EvalArgs {
     double *partials;        // per-block sum of r^2
 };
 hipError_t launch_eval_residual(int prec, const EvalArgs &a, int grid, hipStream_t st);
-hipError_t sync_copy(int prec, const AccumArgs &a, int npend, int ncur, int grid,
-                     hipStream_t st);
 hipError_t reg_partials(int prec, const void *A, int64_t I, int K, const int32_t *rowptr,
                         int weighted, double *partials, int nblocks, hipStream_t st);
 hipError_t sum_partials(const double *partials, int64_t n, double *out, hipStream_t st);

@@ -81,8 +81,9 @@ def test_split_parity_f64(N, dims, nnz, K, cols, T_in, reg, strategy):
     g.close()
 
 
-def test_changing_split_width_uses_standalone_boundary_f64():
-    """A split after a wider one (pending columns exceed the kernel width)."""
+def test_changing_split_width_f64():
+    """Splits narrower than the previous one run at the previous width with
+    zero-padded columns, keeping the residual update fused."""
     dims, K = [50, 40, 30], 12
     note("split width change f64")
     idx, x, A = problem(7, dims, 4000, K)
