@@ -135,6 +135,55 @@ def serve_bench(m, w, rates, seconds, streams, max_batch):
     return out
 
 
+def precision_compare(w, data, sweeps):
+    """Held-out test RMSE and sweep time of the plain FP32 form (one wavefront
+    per row, default tiles) against the batched forms (skew-aware plan, tuned
+    row tiles) in FP32 and BF16 storage, at the workload's C and, for BF16, at
+    a tuned C.  Every form trains from the same seeded start for `sweeps`
+    sweeps; times are the median sweep."""
+    import numpy as np
+    import torch
+
+    from paper_1410_5209_amd import tf
+    from paper_1410_5209_amd.model import SparseCP
+
+    idx, x, idx_t, x_t = data
+    dims = [w.I] * w.N
+    forms = (("fp32-plain", "f32", tf.TF_STRATEGY_PLAIN, None),
+             ("fp32-batched", "f32", tf.TF_STRATEGY_SKEW, [w.C]),
+             ("bf16-batched", "bf16", tf.TF_STRATEGY_SKEW, [w.C]),
+             ("bf16-batched-tunedC", "bf16", tf.TF_STRATEGY_SKEW, [w.C, 16, 32]))
+    out = {}
+    for name, prec, strat, cands in forms:
+        m = SparseCP(dims, idx, x, w.K, w.lam, precision=prec, strategy=strat)
+        C = w.C
+        if cands is not None:
+            C = m.autotune(w.T_in, cands, tune_tiles=True).best_C
+        times = []
+        for _ in range(sweeps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            m.sweep(C, w.T_in)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        pred = m.predict(idx_t)
+        rmse = float(np.sqrt(np.mean((pred - x_t) ** 2)))
+        loss, train_rmse = m.loss()
+        med = float(np.median(times))
+        out[name] = {"C": C, "test_rmse": rmse, "train_rmse": train_rmse, "loss": loss,
+                     "median_sweep_ms": 1e3 * med, "sweeps": sweeps,
+                     "upd_per_s": len(x) * w.K * w.T_in * w.N / med}
+        log(f"{name}: C={C} test RMSE {rmse:.6f}, median sweep {1e3 * med:.1f} ms")
+        m.close()
+        del m
+        torch.cuda.empty_cache()
+    base = out["fp32-plain"]
+    for v in out.values():
+        v["speedup_vs_fp32_plain"] = base["median_sweep_ms"] / v["median_sweep_ms"]
+        v["test_rmse_minus_fp32_plain"] = v["test_rmse"] - base["test_rmse"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,6 +199,9 @@ def main():
     ap.add_argument("--cpu-scale", type=int, default=0,
                     help="oracle sample at 1/scale size (default 4; 40 for the 5-way workload)")
     ap.add_argument("--no-serve", action="store_true", help="skip the fold-in serving runs")
+    ap.add_argument("--no-tune", action="store_true", help="use the default row tiles")
+    ap.add_argument("--precision-compare", action="store_true",
+                    help="with a held-out workload: BF16 vs FP32 test RMSE and sweep time")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--serve-max-batch", type=int, default=512)
@@ -177,6 +229,12 @@ def main():
     log(f"generated {idx.shape[0]} entries in {time.perf_counter() - t0:.1f} s")
 
     torch.cuda.set_device(0)
+    if args.precision_compare:
+        if len(data) != 4:
+            raise SystemExit("--precision-compare needs a workload with a held-out split")
+        res = precision_compare(w, data, w.sweeps)
+        print(json.dumps({"workload": w.name, "precision_compare": res}), flush=True)
+        return
     t0 = time.perf_counter()
     m = SparseCP(dims, idx, x, w.K, w.lam, precision=w.prec, strategy=args.strategy,
                  lane_nnz=args.lane_nnz)
@@ -191,7 +249,9 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    cands = args.autotune or ("8,16,32" if w.name == "sals-5way-zipf-fp32" else None)
+    # the tuner always picks the row tiles per mode; it also picks C when the
+    # workload leaves C open (the 5-way Zipf workload)
+    cands = None if args.no_tune else args.autotune or ("8,16,32" if w.name == "sals-5way-zipf-fp32" else str(w.C))
     C = w.C
     tune = None
     if cands:

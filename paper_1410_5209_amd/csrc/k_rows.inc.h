@@ -136,7 +136,94 @@ __global__ __launch_bounds__(256) void k_accum(AccumArgs a)
             j = jn;
             jn += G;
         }
+    } else if constexpr (CP * NO <= 24) {
+        // First pass of a split: the same pipeline, with each entry's three
+        // segments (current W, previous split's final P, this split's start S
+        // for modes already updated) requested one entry ahead.  Only for
+        // small widths: three segments per other mode, twice, must stay in
+        // registers.
+        auto fetch = [&](const int32_t (&ix)[NO], TA (&w)[NO][CP], TA (&pv)[NO][CP],
+                         TA (&sv)[NO][CP]) {
+#pragma unroll
+            for (int l = 0; l < NO; ++l) {
+                const TS *row_l = reinterpret_cast<const TS *>(a.W[l]) + (int64_t)ix[l] * ld;
+                load_row<CP>(row_l, w[l]);
+                if (a.has_pend)
+                    load_row8<CP>(reinterpret_cast<const TS *>(a.P[l]) + (int64_t)ix[l] * ld, pv[l]);
+                if (a.before[l])
+                    load_row<CP>(reinterpret_cast<const TS *>(a.S[l]) + (int64_t)ix[l] * ld, sv[l]);
+            }
+        };
+        int32_t ii[NO];
+        TR rh = TR(0);
+        TA w[NO][CP], pv[NO][CP], sv[NO][CP];
+        if (j < end) {
+#pragma unroll
+            for (int l = 0; l < NO; ++l) ii[l] = stream_load(a.oidx[l] + j);
+            rh = stream_load(rhat + j);
+            fetch(ii, w, pv, sv);
+        }
+        int64_t jn = j + G;
+        int32_t in_[NO];
+        TR rn = TR(0);
+        if (jn < end) {
+#pragma unroll
+            for (int l = 0; l < NO; ++l) in_[l] = stream_load(a.oidx[l] + jn);
+            rn = stream_load(rhat + jn);
+        }
+        while (j < end) {
+            TA p[CP], tp[CP], ts[CP];
+#pragma unroll
+            for (int c = 0; c < CP; ++c) { p[c] = w[0][c]; tp[c] = own_p[c]; ts[c] = own_s[c]; }
+#pragma unroll
+            for (int l = 1; l < NO; ++l)
+#pragma unroll
+                for (int c = 0; c < CP; ++c) p[c] *= w[l][c];
+#pragma unroll
+            for (int l = 0; l < NO; ++l) {
+                if (a.has_pend) {
+#pragma unroll
+                    for (int c = 0; c < CP; ++c) tp[c] *= pv[l][c];
+                }
+                if (a.before[l]) {
+#pragma unroll
+                    for (int c = 0; c < CP; ++c) ts[c] *= sv[l][c];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < CP; ++c) ts[c] *= w[l][c];
+                }
+            }
+            const TR rcur = rh;
+            const int64_t jcur = j;
+            if (jn < end) {
+                rh = rn;
+                fetch(in_, w, pv, sv);
+                const int64_t jnn = jn + G;
+                if (jnn < end) {
+#pragma unroll
+                    for (int l = 0; l < NO; ++l) in_[l] = stream_load(a.oidx[l] + jnn);
+                    rn = stream_load(rhat + jnn);
+                }
+            }
+            // R-hat of this split from the previous split's residual state
+            TA dr = TA(0), ds = TA(0);
+#pragma unroll
+            for (int c = 0; c < CP; ++c) { dr += tp[c]; ds += ts[c]; }
+            const TA r = ((TA)rcur - dr) + ds;
+            stream_store((TR)r, rhat + jcur);
+
+            int e = 0;
+#pragma unroll
+            for (int c1 = 0; c1 < CP; ++c1)
+#pragma unroll
+                for (int c2 = c1; c2 < CP; ++c2) acc[e++] += p[c1] * p[c2];
+#pragma unroll
+            for (int c = 0; c < CP; ++c) acc[e++] += r * p[c];
+            j = jn;
+            jn += G;
+        }
     } else {
+        // First pass of a split, wider rows: indices and residual prefetched
         int32_t ii[NO];
         TR rh = TR(0);
         if (j < end) {
