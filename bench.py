@@ -195,7 +195,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", default=None,
                     help="comma-separated candidate C values; the sweep then uses the tuned C "
-                         "(default for the 5-way Zipf workload: 8,16,32)")
+                         "(default for the 5-way Zipf workload: 16,32)")
     ap.add_argument("--cpu-scale", type=int, default=0,
                     help="oracle sample at 1/scale size (default 4; 40 for the 5-way workload)")
     ap.add_argument("--no-serve", action="store_true", help="skip the fold-in serving runs")
@@ -251,7 +251,7 @@ def main():
 
     # the tuner always picks the row tiles per mode; it also picks C when the
     # workload leaves C open (the 5-way Zipf workload)
-    cands = None if args.no_tune else args.autotune or ("8,16,32" if w.name == "sals-5way-zipf-fp32" else str(w.C))
+    cands = None if args.no_tune else args.autotune or ("16,32" if w.name == "sals-5way-zipf-fp32" else str(w.C))
     C = w.C
     tune = None
     if cands:

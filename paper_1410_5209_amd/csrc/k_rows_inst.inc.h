@@ -77,7 +77,7 @@ static hipError_t accum_wide(int no, bool first, const AccumArgs &a, int grid, h
 template <int PREC, int CP>
 static hipError_t solve_wide(const SolveArgs &a, hipStream_t st)
 {
-    const int grid = (int)((a.I + 3) / 4);
+    const int grid = (int)((a.I + 7) / 8);
     hipLaunchKernelGGL((k_solve_wide<PREC>), dim3(grid), dim3(256), 0, st, a);
     return hipGetLastError();
 }

@@ -1,19 +1,23 @@
 // Row-update kernels for splits of 32 columns (eq. (SALS) and its B / c,
 // arXiv:1410.5209), FP32 or BF16 storage.
 //
-// k_accum_wide: one wavefront walks a row (or a chunk of one) eight entries at
-//   a time.  Gather phase: lane 8e+q holds columns 4q..4q+3 of entry e, so one
-//   16-byte load per lane fetches eight whole 128-byte factor rows per
-//   instruction; the lane forms its four columns of p_j = prod_{l != n} a^(l)
-//   and, in a split's first pass, its share of the residual update (summed
-//   over the entry's eight lanes).  The eight p vectors go to LDS.
-//   Accumulate phase: lane (bi, bj) owns the 4x4 block (rows 4bi.., columns
-//   4bj..) of B = sum p p^T and, for bj = 0, four entries of c = sum rhat p;
-//   each staged entry is a rank-1 update of that block from two 16-byte LDS
-//   reads.  No cross-lane reduction is needed at the end of a row.
-// k_solve_wide: one wavefront per row: (B + lambda_i I) a = c in FP64 by a
-//   column Cholesky in LDS (text after Theorem 1), then the two triangular
-//   solves; a goes to the W segment of the mode's slab.
+// k_accum_wide: one wavefront walks a row (or a chunk of one) two entries at
+//   a time: lane 32h + c holds column c of the step's entry h, so each half
+//   wavefront reads whole 128-byte factor rows with one coalesced load per
+//   mode.  The lane forms its column of p_j = prod_{l != n} a^(l) (and, in a
+//   split's first pass, its column of the residual update, summed over the
+//   half).  B = sum_j p_j p_j^T is a dense contraction over the row's
+//   entries: one v_mfma_f32_32x32x2f32 per step adds both entries' outer
+//   products to the 32x32 FP32 accumulator; c = sum_j rhat_j p_j stays on
+//   the vector unit.  Entry indices and residuals are staged 64 at a time
+//   (one per lane) and passed to the halves by lane permutes; first-pass
+//   residuals are written back 64 at a time.
+// k_solve_wide: half a wavefront per row: (B + lambda_i I) a = c in FP64 by
+//   Cholesky (text after Theorem 1), M = L L^T computed in place with lane i
+//   holding row i of the lower triangle in registers.  Step j: lane j forms
+//   L(j, j) and y_j; lanes i > j form L(i, j) and publish it in LDS, then
+//   every lane updates its row.  Back substitution L^T a = y: lane k
+//   publishes row k of L and a_k.  a goes to the W segment of the mode's slab.
 #pragma once
 
 #include "dev_common.h"
@@ -23,26 +27,27 @@ namespace tfk {
 constexpr int WCP = 32;                       // columns per split
 constexpr int WNT = WCP * (WCP + 1) / 2;      // 528 Gram entries (upper)
 
-// Four consecutive storage elements -> float (16-byte or 8-byte load).
-__device__ __forceinline__ void load4(const float *__restrict__ p, float (&o)[4])
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Column c of a factor-row segment.  BF16: the lane pair (2k, 2k+1) reads
+// the same aligned 4-byte word and keeps its half (sub-dword loads ran at
+// half the rate of dword loads here).
+__device__ __forceinline__ float load_col(const float *row, int c) { return row[c]; }
+__device__ __forceinline__ float load_col(const bf16 *row, int c)
 {
-    const float4 t = *reinterpret_cast<const float4 *>(p);
-    o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w;
-}
-__device__ __forceinline__ void load4(const bf16 *__restrict__ p, float (&o)[4])
-{
-    const uint2 t = *reinterpret_cast<const uint2 *>(p);
-    o[0] = __uint_as_float(t.x << 16); o[1] = __uint_as_float(t.x & 0xffff0000u);
-    o[2] = __uint_as_float(t.y << 16); o[3] = __uint_as_float(t.y & 0xffff0000u);
+    const uint32_t x = reinterpret_cast<const uint32_t *>(row)[c >> 1];
+    return __uint_as_float((c & 1) ? (x & 0xffff0000u) : (x << 16));
 }
 
-// Sum over the eight lanes of an entry (lanes 8e..8e+7): xor 1, xor 2, then
-// the half-row mirror pairs the two quads.
-__device__ __forceinline__ float sum8(float v)
+// Sum over each 32-lane half: quad swaps, half-row and row mirrors, then the
+// two rows of the half.
+__device__ __forceinline__ float half_sum(float v)
 {
     v += dpp_mov<0xB1>(v);
     v += dpp_mov<0x4E>(v);
     v += dpp_mov<0x141>(v);
+    v += dpp_mov<0x140>(v);
+    v += __shfl_xor(v, 16, 64);
     return v;
 }
 
@@ -53,21 +58,16 @@ __global__ __launch_bounds__(256) void k_accum_wide(AccumArgs a)
     using TR = typename Types<PREC>::TR;
     static_assert(sizeof(typename Types<PREC>::TA) == 4, "wide kernel accumulates in FP32");
     constexpr int NEP = gram_stride(WCP);
-    __shared__ float4 lds_p[4][8][WCP / 4];     // per wave: 8 staged p vectors
-    __shared__ float lds_r[4][8];
+    constexpr int GS = 4;                        // steps whose loads are issued together
 
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int t = blockIdx.x * 4 + wave;
+    const int half = lane >> 5;
+    const int c = lane & 31;
+    const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (t >= a.ntasks) return;  // uniform per wavefront; no block barriers below
     const Task task = a.tasks[t];
     const int64_t ld = a.ld;
     TR *rhat = reinterpret_cast<TR *>(a.rhat);
-
-    const int e = lane >> 3;        // gather phase: entry slot
-    const int q = lane & 7;         // gather phase: column quad
-    const int bi = lane >> 3;       // accumulate phase: block row
-    const int bj = lane & 7;        // accumulate phase: block column
 
     const int nrows = task.kind == 0 ? task.count : 1;
     for (int rr = 0; rr < nrows; ++rr) {
@@ -80,133 +80,108 @@ __global__ __launch_bounds__(256) void k_accum_wide(AccumArgs a)
             end = a.rowptr[row + 1];
             out = reinterpret_cast<float *>(a.gram) + (int64_t)row * NEP;
         } else {
-            const Chunk c = a.chunks[task.base];
-            row = c.row;
-            beg = c.beg;
-            end = c.end;
-            out = reinterpret_cast<float *>(a.gpart) + (int64_t)c.slot * NEP;
+            const Chunk ch = a.chunks[task.base];
+            row = ch.row;
+            beg = ch.beg;
+            end = ch.end;
+            out = reinterpret_cast<float *>(a.gpart) + (int64_t)ch.slot * NEP;
         }
-        float own_p[4], own_s[4];
+        float own_p = 0.f, own_s = 0.f;
         if constexpr (FIRST) {
-            load4(reinterpret_cast<const TS *>(a.Sown) + (int64_t)row * ld + 4 * q, own_s);
-            if (a.has_pend) load4(reinterpret_cast<const TS *>(a.Pown) + (int64_t)row * ld + 4 * q, own_p);
-            else { own_p[0] = own_p[1] = own_p[2] = own_p[3] = 0.f; }
+            own_s = load_col(reinterpret_cast<const TS *>(a.Sown) + (int64_t)row * ld, c);
+            if (a.has_pend) own_p = load_col(reinterpret_cast<const TS *>(a.Pown) + (int64_t)row * ld, c);
         }
-        float acc[4][4], rhs[4];
+        f32x16 acc;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            rhs[u] = 0.f;
+        for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+        float rhs = 0.f;
+
+        for (int64_t s0 = beg; s0 < end; s0 += 64) {
+            // stage 64 entries: lane L holds entry s0 + L
+            const int64_t jl = s0 + lane;
+            const bool lv = jl < end;
+            int32_t bidx[NO];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc[u][v] = 0.f;
-        }
-        // indices and residual of the next step are requested while the
-        // current step's factor rows are gathered and folded in
-        int32_t nx[NO];
-        TR nr = TR(0);
-        if (beg + e < end) {
+            for (int l = 0; l < NO; ++l) bidx[l] = lv ? stream_load(a.oidx[l] + jl) : 0;
+            const float brh = lv ? (float)stream_load(rhat + jl) : 0.f;
+            float rnew = 0.f;
+            const int nstep = (int)((end - s0 + 1) / 2 < 32 ? (end - s0 + 1) / 2 : 32);
+            for (int u0 = 0; u0 < nstep; u0 += GS) {
+                float w[GS][NO], pv[GS][NO], sv[GS][NO], rq[GS];
+                bool val[GS];
 #pragma unroll
-            for (int l = 0; l < NO; ++l) nx[l] = a.oidx[l][beg + e];
-            nr = rhat[beg + e];
-        }
-        for (int64_t s0 = beg; s0 < end; s0 += 8) {
-            const int64_t j = s0 + e;
-            const bool valid = j < end;
-            int32_t ii[NO];
+                for (int q = 0; q < GS; ++q) {
+                    const int src = (2 * (u0 + q) + half) & 63;
+                    val[q] = u0 + q < nstep && s0 + src < end;
+                    int32_t ii[NO];
 #pragma unroll
-            for (int l = 0; l < NO; ++l) ii[l] = nx[l];
-            const TR rcur = nr;
-            if (j + 8 < end) {
-#pragma unroll
-                for (int l = 0; l < NO; ++l) nx[l] = a.oidx[l][j + 8];
-                nr = rhat[j + 8];
-            }
-            float p[4] = {0.f, 0.f, 0.f, 0.f};
-            float r = 0.f, dr = 0.f, ds = 0.f;   // this lane's four columns of the update
-            if (valid) {
-                r = (float)rcur;
-                float w[NO][4];
-#pragma unroll
-                for (int l = 0; l < NO; ++l)
-                    load4(reinterpret_cast<const TS *>(a.W[l]) + (int64_t)ii[l] * ld + 4 * q, w[l]);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) p[c] = w[0][c];
-#pragma unroll
-                for (int l = 1; l < NO; ++l)
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) p[c] *= w[l][c];
-                if constexpr (FIRST) {
-                    float tp[4], ts[4];
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) { tp[c] = own_p[c]; ts[c] = own_s[c]; }
+                    for (int l = 0; l < NO; ++l) ii[l] = __shfl(bidx[l], src, 64);
+                    rq[q] = __shfl(brh, src, 64);
 #pragma unroll
                     for (int l = 0; l < NO; ++l) {
-                        if (a.has_pend) {
-                            float v[4];
-                            load4(reinterpret_cast<const TS *>(a.P[l]) + (int64_t)ii[l] * ld + 4 * q, v);
-#pragma unroll
-                            for (int c = 0; c < 4; ++c) tp[c] *= v[c];
-                        }
-                        if (a.before[l]) {
-                            float v[4];
-                            load4(reinterpret_cast<const TS *>(a.S[l]) + (int64_t)ii[l] * ld + 4 * q, v);
-#pragma unroll
-                            for (int c = 0; c < 4; ++c) ts[c] *= v[c];
-                        } else {
-#pragma unroll
-                            for (int c = 0; c < 4; ++c) ts[c] *= w[l][c];
+                        w[q][l] = pv[q][l] = sv[q][l] = 0.f;
+                        if (val[q]) {
+                            const int64_t off = (int64_t)ii[l] * ld;
+                            w[q][l] = load_col(reinterpret_cast<const TS *>(a.W[l]) + off, c);
+                            if constexpr (FIRST) {
+                                if (a.has_pend) pv[q][l] = load_col(reinterpret_cast<const TS *>(a.P[l]) + off, c);
+                                if (a.before[l]) sv[q][l] = load_col(reinterpret_cast<const TS *>(a.S[l]) + off, c);
+                            }
                         }
                     }
-                    dr = (tp[0] + tp[1]) + (tp[2] + tp[3]);
-                    ds = (ts[0] + ts[1]) + (ts[2] + ts[3]);
+                }
+#pragma unroll
+                for (int q = 0; q < GS; ++q) {
+                    float p = val[q] ? w[q][0] : 0.f;
+#pragma unroll
+                    for (int l = 1; l < NO; ++l) p *= w[q][l];
+                    float r = rq[q];
+                    if constexpr (FIRST) {
+                        // R-hat of this split: the previous split's columns
+                        // (final values) out, this split's (start values) in
+                        float tp = val[q] ? own_p : 0.f, ts = val[q] ? own_s : 0.f;
+#pragma unroll
+                        for (int l = 0; l < NO; ++l) {
+                            tp *= pv[q][l];
+                            ts *= a.before[l] ? sv[q][l] : w[q][l];
+                        }
+                        r = (r - half_sum(tp)) + half_sum(ts);
+                        const float rh0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r), 0));
+                        const float rh1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r), 32));
+                        const int u = u0 + q;
+                        if (lane == 2 * u) rnew = rh0;
+                        if (lane == 2 * u + 1) rnew = rh1;
+                    }
+                    if (!val[q]) r = 0.f;
+                    rhs += r * p;
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(p, p, acc, 0, 0, 0);
                 }
             }
             if constexpr (FIRST) {
-                // R-hat of this split: subtract the previous split's columns
-                // (final values), add this split's (start values); the sums
-                // over the 32 columns run over the entry's eight lanes
-                dr = sum8(dr);
-                ds = sum8(ds);
-                r = (r - dr) + ds;
-                if (valid && q == 0) rhat[j] = (TR)r;
+                if (lv) stream_store((TR)rnew, rhat + jl);
             }
-            lds_p[wave][e][q] = make_float4(p[0], p[1], p[2], p[3]);
-            if (q == 0) lds_r[wave][e] = valid ? r : 0.f;
-            __builtin_amdgcn_wave_barrier();
-            // accumulate phase: rank-1 updates of this lane's 4x4 block
-#pragma unroll
-            for (int ee = 0; ee < 8; ++ee) {
-                const float4 x = lds_p[wave][ee][bi];
-                const float4 y = lds_p[wave][ee][bj];
-                const float xs[4] = {x.x, x.y, x.z, x.w};
-                const float ys[4] = {y.x, y.y, y.z, y.w};
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) acc[u][v] += xs[u] * ys[v];
-                if (bj == 0) {
-                    const float rr2 = lds_r[wave][ee];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) rhs[u] += rr2 * xs[u];
-                }
-            }
-            __builtin_amdgcn_wave_barrier();
         }
-        // Gram record: upper triangle of B, then c
-        if (bi <= bj) {
+        rhs += __shfl_xor(rhs, 32, 64);
+        // Gram record: upper triangle of B, then c.  Accumulator register r
+        // of lane 32h + c holds B(8 (r / 4) + 4 h + r % 4, c).
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int c1 = 4 * bi + u, c2 = 4 * bj + v;
-                    if (c1 <= c2) out[c1 * WCP - c1 * (c1 - 1) / 2 + (c2 - c1)] = acc[u][v];
-                }
+        for (int r = 0; r < 16; ++r) {
+            const int i = 8 * (r / 4) + 4 * half + (r % 4);
+            if (i <= c) out[i * WCP - i * (i - 1) / 2 + (c - i)] = acc[r];
         }
-        if (bj == 0) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) out[WNT + 4 * bi + u] = rhs[u];
-        }
+        if (half == 0) out[WNT + c] = rhs;
         if (lane < NEP - WNT - WCP) out[WNT + WCP + lane] = 0.f;
     }
+}
+
+// 1 / sqrt(d) for d > 0: hardware estimate, then two steps of Newton's
+// iteration r <- r (3 - d r^2) / 2 (each roughly doubles the correct bits).
+__device__ __forceinline__ double rsqrt_nr(double d)
+{
+    double r = __builtin_amdgcn_rsq(d);
+    r = r * (1.5 - 0.5 * d * r * r);
+    r = r * (1.5 - 0.5 * d * r * r);
+    return r;
 }
 
 template <int PREC>
@@ -214,76 +189,109 @@ __global__ __launch_bounds__(256) void k_solve_wide(SolveArgs a)
 {
     using TS = typename Types<PREC>::TS;
     constexpr int NEP = gram_stride(WCP);
-    __shared__ double Ls[4][WNT];
-    __shared__ double ys[4][WCP];
+    constexpr int NV = NEP / 4;
+    __shared__ float4 rec[8][NV];           // the block's eight Gram records
+    __shared__ double pub[8][WCP + 2];      // per row: published column / row of L, [WCP..] scalars
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int64_t row = (int64_t)blockIdx.x * 4 + wave;
-    if (row >= a.I) return;
-    const int64_t cnt = (int64_t)a.rowptr[row + 1] - a.rowptr[row];
-    TS *o = reinterpret_cast<TS *>(a.W) + row * a.ld;
-    if (cnt == 0) {
-        if (lane < WCP) o[lane] = store_cast<TS>(0.0);
-        return;
-    }
-    double *L = Ls[wave];
-    double *y = ys[wave];
-    const float *g = reinterpret_cast<const float *>(a.gram) + row * NEP;
-    // upper record (c1 <= c2) -> packed lower L(c2, c1)
-    for (int c1 = 0; c1 < WCP; ++c1) {
-        const int len = WCP - c1;
-        const int base = c1 * WCP - c1 * (c1 - 1) / 2;
-        for (int d = lane; d < len; d += 64) {
-            const int c2 = c1 + d;
-            L[c2 * (c2 + 1) / 2 + c1] = (double)g[base + d];
-        }
-    }
-    const double lam = a.reg_mode ? a.lambda * (double)cnt : a.lambda;
-    if (lane < WCP) {
-        y[lane] = (double)g[WNT + lane];
-        L[lane * (lane + 1) / 2 + lane] += lam;
+    const int half = lane >> 5;
+    const int i = lane & 31;
+    const int slot = 2 * wave + half;
+    const int64_t row0 = (int64_t)blockIdx.x * 8 + 2 * wave;
+    const int64_t row = row0 + half;
+
+    // the wavefront's two records, coalesced, into LDS
+    const float4 *gsrc = reinterpret_cast<const float4 *>(a.gram);
+    for (int v = lane; v < 2 * NV; v += 64) {
+        const int r = v >= NV ? 1 : 0;
+        const int q = v - r * NV;
+        if (row0 + r < a.I) rec[2 * wave + r][q] = gsrc[(row0 + r) * NV + q];
     }
     __builtin_amdgcn_wave_barrier();
+
+    const bool valid = row < a.I;
+    const int64_t cnt = valid ? (int64_t)a.rowptr[row + 1] - a.rowptr[row] : 0;
+    const bool live = cnt > 0;
+    const float *rf = reinterpret_cast<const float *>(rec[slot]);
+    // lane i: M(i, k) for k <= i, which is record entry (k, i) of the upper
+    // triangle, and c_i; an empty or absent row solves the identity system.
+    // Slots k > i are scratch.
+    const double lam = a.reg_mode ? a.lambda * (double)cnt : a.lambda;
+    double m[WCP];
+#pragma unroll
+    for (int k = 0; k < WCP; ++k) {
+        const int idx = k * WCP - k * (k - 1) / 2 - k + i;
+        m[k] = (live && k <= i) ? (double)rf[idx] : 0.0;
+        if (k == i) m[k] = live ? m[k] + lam : 1.0;
+    }
+    double c = live ? (double)rf[WNT + i] : 0.0;
+
+    double *u = pub[slot];
     bool ok = true;
+    double rinv = 1.0;
+#pragma unroll
     for (int j = 0; j < WCP; ++j) {
-        const double d = L[j * (j + 1) / 2 + j];
-        ok = ok && d > 0.0;
-        const double ljj = sqrt(d > 0.0 ? d : 1.0);
+        if (i == j) {
+            const double d = m[j];
+            ok = d > 0.0;
+            const double dd = ok ? d : 1.0;
+            rinv = rsqrt_nr(dd);        // 1 / L(j, j)
+            m[j] = dd * rinv;
+            c *= rinv;                  // y_j of L y = c
+            u[WCP] = rinv;
+            u[WCP + 1] = c;
+        }
         __builtin_amdgcn_wave_barrier();
-        if (lane == j) L[j * (j + 1) / 2 + j] = ljj;
-        if (lane > j && lane < WCP) L[lane * (lane + 1) / 2 + j] /= ljj;
+        const double dj = u[WCP], yj = u[WCP + 1];
+        double lij = 0.0;
+        if (i > j) {
+            lij = m[j] * dj;            // L(i, j)
+            m[j] = lij;
+            c -= lij * yj;
+            u[i] = lij;
+        }
         __builtin_amdgcn_wave_barrier();
-        // trailing update, pairs (i, k) with j < k <= i < WCP
-        const int n = WCP - 1 - j;
-        const int T = n * (n + 1) / 2;
-        for (int pp = lane; pp < T; pp += 64) {
-            int r = (int)((sqrtf(8.0f * (float)pp + 1.0f) - 1.0f) * 0.5f);
-            while ((r + 1) * (r + 2) / 2 <= pp) ++r;
-            while (r * (r + 1) / 2 > pp) --r;
-            const int i = j + 1 + r, k = j + 1 + (pp - r * (r + 1) / 2);
-            L[i * (i + 1) / 2 + k] -= L[i * (i + 1) / 2 + j] * L[k * (k + 1) / 2 + j];
+        // M(i, k) -= L(i, j) L(k, j); lanes i <= j have lij = 0 and only
+        // scratch slots at k > j.  The empty asm pins each update to this
+        // step (left to itself the compiler defers them and keeps the
+        // published column live in registers across steps).
+        double col[WCP];
+#pragma unroll
+        for (int k = j + 1; k < WCP; ++k) col[k] = u[k];
+#pragma unroll
+        for (int k = j + 1; k < WCP; ++k) {
+            m[k] -= lij * col[k];
+            asm volatile("" : "+v"(m[k]));
         }
         __builtin_amdgcn_wave_barrier();
     }
-    if (!ok) {
-        if (lane == 0) atomicMin(a.bad, (unsigned long long)row);
+    // L^T a = y, last unknown first
+#pragma unroll
+    for (int k = WCP - 1; k >= 0; --k) {
+        if (i == k) {
+            c *= rinv;                  // a_k
+#pragma unroll
+            for (int t = 0; t < k; ++t) u[t] = m[t];
+            u[WCP + 1] = c;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (i < k) c -= u[i] * u[WCP + 1];
+        __builtin_amdgcn_wave_barrier();
+    }
+
+    const unsigned long long bad = __ballot(!ok);
+    const bool row_bad = ((bad >> (32 * half)) & 0xffffffffull) != 0ull;
+    if (!valid) return;
+    TS *o = reinterpret_cast<TS *>(a.W) + row * a.ld;
+    if (!live) {
+        o[i] = store_cast<TS>(0.0);
         return;
     }
-    for (int k = 0; k < WCP; ++k) {          // L y = c
-        const double yk = y[k] / L[k * (k + 1) / 2 + k];
-        __builtin_amdgcn_wave_barrier();
-        if (lane == k) y[k] = yk;
-        if (lane > k && lane < WCP) y[lane] -= L[lane * (lane + 1) / 2 + k] * yk;
-        __builtin_amdgcn_wave_barrier();
+    if (row_bad) {
+        if (i == 0) atomicMin(a.bad, (unsigned long long)row);
+        return;
     }
-    for (int k = WCP - 1; k >= 0; --k) {     // L^T a = y
-        const double ak = y[k] / L[k * (k + 1) / 2 + k];
-        __builtin_amdgcn_wave_barrier();
-        if (lane == k) y[k] = ak;
-        if (lane < k) y[lane] -= L[k * (k + 1) / 2 + lane] * ak;
-        __builtin_amdgcn_wave_barrier();
-    }
-    if (lane < WCP) o[lane] = store_cast<TS>(y[lane]);
+    o[i] = store_cast<TS>(c);
 }
 
 }  // namespace tfk

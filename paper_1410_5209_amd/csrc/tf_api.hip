@@ -121,15 +121,20 @@ constexpr size_t kSlabRowBytes = 384;
 // of columns: segments of whole 8-byte units (so W and S start 16-byte
 // aligned), rows padded to whole 128-byte lines so that no row straddles a
 // line it does not need.
-void slab_geometry(tf_ctx *c, int width)
+tf_status slab_geometry(tf_ctx *c, int width)
 {
     const int64_t q = c->prec == P_BF16 ? 4 : 2;
     const int64_t sw = (std::max(width, 1) + q - 1) / q * q;
     const int64_t vw = vec_w(c->prec);
     const int64_t need = std::max<int64_t>(3 * sw, 2 * sw + (sw + vw - 1) / vw * vw);
     const int64_t per_line = 128 / (int64_t)ts_size(c->prec);
+    const int64_t lines = (need + per_line - 1) / per_line;
+    if (lines * 128 > (int64_t)kSlabRowBytes)
+        return CTX_FAIL(c, TF_E_UNSUPPORTED, "slab row of %lld lines exceeds the allocation",
+                        (long long)lines);
     c->sw = sw;
-    c->ld = (need + per_line - 1) / per_line * per_line;
+    c->ld = lines * per_line;
+    return TF_OK;
 }
 
 const void *seg(const tf_ctx *c, const void *Z, int which)
@@ -231,7 +236,7 @@ tf_status run_split(tf_ctx *c, const int32_t *cols, int ncols, int T_in)
     if (s != TF_OK) return s;
     const int npend = (int)c->pend.size();
     if (npend > CP) return CTX_FAIL(c, TF_E_UNSUPPORTED, "pending columns exceed the kernel width");
-    slab_geometry(c, std::max(CP, npend));
+    if ((s = slab_geometry(c, std::max(CP, npend))) != TF_OK) return s;
     if ((s = upload_cols(c, cols, ncols)) != TF_OK) return s;
     const int32_t *d_cur = c->d_cols;
     const int32_t *d_pend = c->d_cols + c->K;
@@ -324,8 +329,8 @@ tf_status eval_residual(tf_ctx *c, double *d_rout, double *se_out)
 {
     // the pending columns go into the W segment of the slabs
     const int npend = (int)c->pend.size();
-    slab_geometry(c, std::max(npend, 1));
-    tf_status s;
+    tf_status s = slab_geometry(c, std::max(npend, 1));
+    if (s != TF_OK) return s;
     if (npend > 0) {
         if ((s = upload_cols(c, c->pend.data(), npend)) != TF_OK) return s;
         if ((s = pack_all(c, c->d_cols, npend, c->d_cols, 0)) != TF_OK) return s;
@@ -677,8 +682,8 @@ tf_status trial_slabs(tf_ctx *c, int C, int *CP_out, int *npend_out)
     std::vector<int32_t> cols(c->order.begin(), c->order.begin() + C);
     const auto saved = c->pend;
     c->pend.assign(c->order.end() - C, c->order.end());
-    slab_geometry(c, CP);
-    s = upload_cols(c, cols.data(), C);
+    s = slab_geometry(c, CP);
+    if (s == TF_OK) s = upload_cols(c, cols.data(), C);
     c->pend = saved;
     if (s != TF_OK) return s;
     if ((s = pack_all(c, c->d_cols, C, c->d_cols + c->K, npend)) != TF_OK) return s;
