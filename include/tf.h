@@ -72,7 +72,23 @@ typedef struct tf_options {
                                   (0 = 4096) */
     int32_t chunk_nnz;         /* SKEW: nonzeros per chunk of a split row
                                   (0 = 2048) */
+    int32_t resid_share;       /* TF_RESID_*: where the row passes of modes
+                                  2..N read R-hat (default TF_RESID_AUTO) */
 } tf_options;
+
+/* Residual placement.  Mode 1 keeps R-hat in its own row order and forms it
+ * in its first pass of each split (eq. (SALS_R) of the previous split plus
+ * the R-hat step of Algorithm 1), which needs the previous split's final and
+ * this split's starting columns of every factor row it gathers.  Another
+ * mode either keeps its own copy the same way (TF_RESID_OWN) or reads mode
+ * 1's copy through a permutation (TF_RESID_SHARED: one random 4- or 8-byte
+ * read per entry and pass, no residual work).  TF_RESID_AUTO picks, per
+ * mode and split, the choice with fewer random cache-line requests per
+ * entry given the split's slab layout and T_in.  The choice changes only
+ * rounding. */
+#define TF_RESID_AUTO 0
+#define TF_RESID_OWN 1
+#define TF_RESID_SHARED 2
 
 typedef struct tf_ctx tf_ctx;
 

@@ -345,6 +345,47 @@ hipError_t gather_residual(int prec, const double *r_in, const int32_t *perm, in
     return hipGetLastError();
 }
 
+// Position in the mode-0 order of the entry at each position of another
+// mode's order: inv[perm0[p]] = p, then out[q] = inv[permn[q]].
+__global__ void k_invert_perm(const int32_t *perm, int64_t nnz, int32_t *inv)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nnz) inv[perm[p]] = (int32_t)p;
+}
+
+__global__ void k_gather_i32(const int32_t *in, const int32_t *idx, int64_t nnz, int32_t *out)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nnz) out[q] = in[idx[q]];
+}
+
+hipError_t compose_with_mode0(const int32_t *perm0, const int32_t *permn, int64_t nnz,
+                              int32_t *inv_scratch, int32_t *out, hipStream_t st)
+{
+    const int64_t grid = (nnz + 255) / 256;
+    hipLaunchKernelGGL(k_invert_perm, dim3((unsigned)grid), dim3(256), 0, st, perm0, nnz, inv_scratch);
+    hipLaunchKernelGGL(k_gather_i32, dim3((unsigned)grid), dim3(256), 0, st, inv_scratch, permn, nnz, out);
+    return hipGetLastError();
+}
+
+template <typename TR>
+__global__ void k_gather_copy(const TR *in, const int32_t *idx, int64_t nnz, TR *out)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nnz) out[q] = in[idx[q]];
+}
+
+hipError_t gather_copy(int prec, const void *in, const int32_t *idx, int64_t nnz, void *out,
+                       hipStream_t st)
+{
+    const int64_t grid = (nnz + 255) / 256;
+    if (prec == P_F64)
+        hipLaunchKernelGGL(k_gather_copy<double>, dim3((unsigned)grid), dim3(256), 0, st, (const double *)in, idx, nnz, (double *)out);
+    else
+        hipLaunchKernelGGL(k_gather_copy<float>, dim3((unsigned)grid), dim3(256), 0, st, (const float *)in, idx, nnz, (float *)out);
+    return hipGetLastError();
+}
+
 template <int PREC>
 __global__ void k_to_f64(const void *A, int64_t n, double *out)
 {

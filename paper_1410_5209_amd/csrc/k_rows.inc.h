@@ -86,13 +86,18 @@ __global__ __launch_bounds__(256) void k_accum(AccumArgs a)
         // Software pipeline: the factor rows of the next entry are requested
         // before the current entry is folded in, and the indices one entry
         // further ahead, so a lane keeps gathers in flight while it computes.
+        // (with a.rperm the residual is read from another mode's copy)
+        const int32_t *rperm = a.rperm;
+        auto load_r = [&](int64_t jj) -> TR {
+            return rperm ? rhat[stream_load(rperm + jj)] : stream_load(rhat + jj);
+        };
         int32_t ii[NO];
         TR rh = TR(0);
         TA w[NO][CP];
         if (j < end) {
 #pragma unroll
             for (int l = 0; l < NO; ++l) ii[l] = stream_load(a.oidx[l] + j);
-            rh = stream_load(rhat + j);
+            rh = load_r(j);
 #pragma unroll
             for (int l = 0; l < NO; ++l)
                 load_row<CP>(reinterpret_cast<const TS *>(a.W[l]) + (int64_t)ii[l] * ld, w[l]);
@@ -103,7 +108,7 @@ __global__ __launch_bounds__(256) void k_accum(AccumArgs a)
         if (jn < end) {
 #pragma unroll
             for (int l = 0; l < NO; ++l) in_[l] = stream_load(a.oidx[l] + jn);
-            rn = stream_load(rhat + jn);
+            rn = load_r(jn);
         }
         while (j < end) {
             TA p[CP];
@@ -123,7 +128,7 @@ __global__ __launch_bounds__(256) void k_accum(AccumArgs a)
                 if (jnn < end) {
 #pragma unroll
                     for (int l = 0; l < NO; ++l) in_[l] = stream_load(a.oidx[l] + jnn);
-                    rn = stream_load(rhat + jnn);
+                    rn = load_r(jnn);
                 }
             }
             int e = 0;

@@ -103,7 +103,8 @@ __global__ __launch_bounds__(256) void k_accum_wide(AccumArgs a)
             int32_t bidx[NO];
 #pragma unroll
             for (int l = 0; l < NO; ++l) bidx[l] = lv ? stream_load(a.oidx[l] + jl) : 0;
-            const float brh = lv ? (float)stream_load(rhat + jl) : 0.f;
+            float brh = 0.f;
+            if (lv) brh = (float)(a.rperm ? rhat[stream_load(a.rperm + jl)] : stream_load(rhat + jl));
             float rnew = 0.f;
             const int nstep = (int)((end - s0 + 1) / 2 < 32 ? (end - s0 + 1) / 2 : 32);
             for (int u0 = 0; u0 < nstep; u0 += GS) {

@@ -222,6 +222,76 @@ tf_status upload_cols(tf_ctx *c, const int32_t *cols, int ncols)
     return TF_OK;
 }
 
+// 128-byte lines a pass touches in one gathered slab row: the W segment,
+// plus P and S when asked (each segment read over CP columns).
+int row_lines(const tf_ctx *c, int CP, bool p, bool s)
+{
+    const int64_t sf = (int64_t)ts_size(c->prec), seg_b = c->sw * sf, len = CP * sf;
+    bool used[8] = {false};
+    auto mark = [&](int k) {
+        for (int64_t b = k * seg_b; b < k * seg_b + len; b += 8) used[std::min<int64_t>(b / 128, 7)] = true;
+    };
+    mark(0);
+    if (p) mark(1);
+    if (s) mark(2);
+    int n = 0;
+    for (bool u : used) n += u ? 1 : 0;
+    return n;
+}
+
+// Whether mode n (>= 1) reads mode 0's residual copy in this split: the
+// option, or (auto) the smaller count of random line requests per entry
+// over the split's T_in passes.  Own copy: the first pass gathers W, P (when
+// columns are pending) and S (modes already updated) of every other mode.
+// Shared: W only, plus one residual read per pass.
+bool want_shared(const tf_ctx *c, int n, int CP, int npend, int T_in)
+{
+    if (n == 0 || c->opt.resid_share == TF_RESID_OWN) return false;
+    if (c->opt.resid_share == TF_RESID_SHARED) return true;
+    int own = 0, shared = T_in;
+    for (int l = 0; l < c->N; ++l) {
+        if (l == n) continue;
+        const int w = row_lines(c, CP, false, false);
+        own += row_lines(c, CP, npend > 0, l < n) + (T_in - 1) * w;
+        shared += T_in * w;
+    }
+    return shared < own;
+}
+
+// pos0 of mode n: position in mode 0's order of each entry of mode n's order.
+tf_status ensure_pos0(tf_ctx *c, int n)
+{
+    auto &md = c->m[n];
+    if (md.pos0) return TF_OK;
+    int32_t *inv = nullptr;
+    HIPCHK(c, hipMalloc(&md.pos0, (size_t)c->nnz * sizeof(int32_t)));
+    HIPCHK(c, hipMalloc(&inv, (size_t)c->nnz * sizeof(int32_t)));
+    hipError_t e = compose_with_mode0(c->m[0].perm, md.perm, c->nnz, inv, md.pos0, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(inv);
+    if (e != hipSuccess) return CTX_FAIL(c, TF_E_DEVICE, "pos0: %s", hipGetErrorString(e));
+    return TF_OK;
+}
+
+// Residual sources for a split; a mode returning to its own copy first takes
+// mode 0's R-hat of the previous split (the value its copy would hold).
+tf_status place_residuals(tf_ctx *c, int CP, int npend, int T_in)
+{
+    for (int n = 1; n < c->N; ++n) {
+        auto &md = c->m[n];
+        const bool sh = want_shared(c, n, CP, npend, T_in);
+        if (sh) {
+            tf_status s = ensure_pos0(c, n);
+            if (s != TF_OK) return s;
+        } else if (!md.fresh) {
+            HIPCHK(c, gather_copy(c->prec, c->m[0].rhat, md.pos0, c->nnz, md.rhat, c->stream));
+            md.fresh = true;
+        }
+        md.shared = sh;
+    }
+    return TF_OK;
+}
+
 // One split of Algorithm 1 on columns cols[0..ncols).
 tf_status run_split(tf_ctx *c, const int32_t *cols, int ncols, int T_in)
 {
@@ -241,6 +311,8 @@ tf_status run_split(tf_ctx *c, const int32_t *cols, int ncols, int T_in)
     const int32_t *d_cur = c->d_cols;
     const int32_t *d_pend = c->d_cols + c->K;
 
+    if ((s = place_residuals(c, CP, npend, T_in)) != TF_OK) return s;
+
     // slabs at the start of the split: S (snapshot) and W (working copy) hold
     // the split's columns, P the previous split's columns (final values)
     if ((s = pack_all(c, d_cur, ncols, d_pend, npend)) != TF_OK) return s;
@@ -249,8 +321,13 @@ tf_status run_split(tf_ctx *c, const int32_t *cols, int ncols, int T_in)
         for (int n = 0; n < c->N; ++n) {
             auto &md = c->m[n];
             const bool first = it == 0;
+            const bool sh = n > 0 && md.shared;
             AccumArgs a;
-            fill_accum_args(c, n, first ? npend : 0, &a);
+            fill_accum_args(c, n, first && !sh ? npend : 0, &a);
+            if (sh) {
+                a.rhat = c->m[0].rhat;
+                a.rperm = md.pos0;
+            }
             const int grid = (md.ntasks + 3) / 4;
             if (grid > 0) {
                 hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -259,7 +336,7 @@ tf_status run_split(tf_ctx *c, const int32_t *cols, int ncols, int T_in)
                     e1 = take_event(c);
                     if (e0) HIPCHK(c, hipEventRecord(e0, c->stream));
                 }
-                HIPCHK(c, launch_accum(c->prec, CP, c->N - 1, first, a, grid, c->stream));
+                HIPCHK(c, launch_accum(c->prec, CP, c->N - 1, first && !sh, a, grid, c->stream));
                 if (c->profiling && e0 && e1) {
                     HIPCHK(c, hipEventRecord(e1, c->stream));
                     c->ev_pending.push_back(
@@ -284,6 +361,7 @@ tf_status run_split(tf_ctx *c, const int32_t *cols, int ncols, int T_in)
     for (int l = 0; l < c->N; ++l) {
         auto &md = c->m[l];
         HIPCHK(c, unpack_slab(c->prec, md.Z, md.I, c->K, d_cur, ncols, c->ld, md.A, c->stream));
+        if (md.shared) md.fresh = false;
     }
     c->pend.assign(cols, cols + ncols);
     return TF_OK;
@@ -379,6 +457,7 @@ void destroy_ctx(tf_ctx *c)
         dfree(md.rhat); dfree(md.A); dfree(md.Z);
         dfree(md.tasks); dfree(md.items); dfree(md.chunks);
         dfree(md.split_rows); dfree(md.split_chunk_ptr);
+        dfree(md.pos0);
     }
     dfree(c->gram); dfree(c->gpart); dfree(c->d_cols); dfree(c->d_bad);
     dfree(c->d_partials); dfree(c->d_scalar);
@@ -533,6 +612,7 @@ void tf_default_options(tf_options *opt)
     opt->lane_nnz = 2;
     opt->split_threshold = 4096;
     opt->chunk_nnz = 2048;
+    opt->resid_share = TF_RESID_AUTO;
 }
 
 const char *tf_last_error(const tf_ctx *ctx)
@@ -569,6 +649,8 @@ tf_status tf_init(tf_ctx **out, int32_t N, const int64_t *dims, int64_t nnz, con
         return set_err(&g_init_err, TF_E_INVALID, "bad strategy");
     if (o.lane_nnz < 0 || o.split_threshold < 0 || o.chunk_nnz < 0)
         return set_err(&g_init_err, TF_E_INVALID, "negative tuning option");
+    if (o.resid_share < TF_RESID_AUTO || o.resid_share > TF_RESID_SHARED)
+        return set_err(&g_init_err, TF_E_INVALID, "bad resid_share");
     if (o.lane_nnz == 0) o.lane_nnz = 2;
     if (o.split_threshold == 0) o.split_threshold = 4096;
     if (o.chunk_nnz == 0) o.chunk_nnz = 2048;
@@ -641,13 +723,16 @@ tf_status tf_sweep(tf_ctx *ctx, int32_t C, int32_t T_in)
 namespace {
 
 // One timed pass on mode n (accumulation, chunk sums, solve) reading the
-// residual from `rhat`; returns milliseconds.
-tf_status time_pass(tf_ctx *c, int n, int CP, int npend, bool first, void *rhat, double *ms)
+// residual from `rhat` (through `rperm` when given: a plain pass on mode
+// 0's copy); returns milliseconds.
+tf_status time_pass(tf_ctx *c, int n, int CP, int npend, bool first, void *rhat, double *ms,
+                    const int32_t *rperm = nullptr)
 {
     auto &md = c->m[n];
     AccumArgs a;
     fill_accum_args(c, n, first ? npend : 0, &a);
     a.rhat = rhat;
+    a.rperm = rperm;
     hipEvent_t e0 = take_event(c), e1 = take_event(c);
     if (!e0 || !e1) return CTX_FAIL(c, TF_E_DEVICE, "event creation failed");
     HIPCHK(c, hipEventRecord(e0, c->stream));
@@ -692,6 +777,31 @@ tf_status trial_slabs(tf_ctx *c, int C, int *CP_out, int *npend_out)
     return TF_OK;
 }
 
+// Times of mode n's first and later passes in a trial split, with the
+// residual placement a real split of this width would use; own-copy passes
+// work on a scratch copy of the residual.
+tf_status time_mode(tf_ctx *c, int n, int CP, int npend, int T_in, void *scratch, double *t1,
+                    double *t2)
+{
+    tf_status s;
+    *t1 = *t2 = 0.0;
+    if (want_shared(c, n, CP, npend, T_in)) {
+        if ((s = ensure_pos0(c, n)) != TF_OK) return s;
+        if ((s = time_pass(c, n, CP, 0, false, c->m[0].rhat, t1, c->m[n].pos0)) != TF_OK) return s;
+        *t2 = *t1;
+        return TF_OK;
+    }
+    if (!c->m[n].fresh) {
+        HIPCHK(c, gather_copy(c->prec, c->m[0].rhat, c->m[n].pos0, c->nnz, scratch, c->stream));
+    } else {
+        HIPCHK(c, hipMemcpyAsync(scratch, c->m[n].rhat, (size_t)c->nnz * tr_size(c->prec),
+                                 hipMemcpyDeviceToDevice, c->stream));
+    }
+    if ((s = time_pass(c, n, CP, npend, true, scratch, t1)) != TF_OK) return s;
+    if (T_in > 1 && (s = time_pass(c, n, CP, npend, false, scratch, t2)) != TF_OK) return s;
+    return TF_OK;
+}
+
 }  // namespace
 
 extern "C" tf_status tf_autotune(tf_ctx *ctx, int32_t T_in, const int32_t *h_cands, int32_t ncand,
@@ -720,11 +830,8 @@ extern "C" tf_status tf_autotune(tf_ctx *ctx, int32_t T_in, const int32_t *h_can
         if ((s = trial_slabs(ctx, C, &CP, &npend)) != TF_OK) return s;
         double split_ms = 0.0;
         for (int n = 0; n < ctx->N; ++n) {
-            HIPCHK(ctx, hipMemcpyAsync(scratch, ctx->m[n].rhat, (size_t)ctx->nnz * tr_size(ctx->prec),
-                                       hipMemcpyDeviceToDevice, ctx->stream));
             double t1 = 0.0, t2 = 0.0;
-            if ((s = time_pass(ctx, n, CP, npend, true, scratch, &t1)) != TF_OK) return s;
-            if (T_in > 1 && (s = time_pass(ctx, n, CP, npend, false, scratch, &t2)) != TF_OK) return s;
+            if ((s = time_mode(ctx, n, CP, npend, T_in, scratch, &t1, &t2)) != TF_OK) return s;
             split_ms += t1 + (T_in - 1) * t2;
         }
         // slab packing and write-back: time one packing of all modes, count it twice
@@ -757,11 +864,8 @@ extern "C" tf_status tf_autotune(tf_ctx *ctx, int32_t T_in, const int32_t *h_can
                 for (int ch : chunks) {
                     if ((s = apply_plan(ctx, n, lane, 2 * ch, ch)) != TF_OK) return s;
                     if ((s = trial_slabs(ctx, bestC, &CP, &npend)) != TF_OK) return s;
-                    HIPCHK(ctx, hipMemcpyAsync(scratch, ctx->m[n].rhat, (size_t)ctx->nnz * tr_size(ctx->prec),
-                                               hipMemcpyDeviceToDevice, ctx->stream));
                     double t1 = 0.0, t2 = 0.0;
-                    if ((s = time_pass(ctx, n, CP, npend, true, scratch, &t1)) != TF_OK) return s;
-                    if (T_in > 1 && (s = time_pass(ctx, n, CP, npend, false, scratch, &t2)) != TF_OK) return s;
+                    if ((s = time_mode(ctx, n, CP, npend, T_in, scratch, &t1, &t2)) != TF_OK) return s;
                     const double t = t1 + (T_in - 1) * t2;
                     if (t < tbest) { tbest = t; bl = lane; bs = 2 * ch; bc = ch; }
                 }
@@ -863,6 +967,7 @@ tf_status tf_resync(tf_ctx *ctx)
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     dfree(r);
     if (e != hipSuccess) return CTX_FAIL(ctx, TF_E_DEVICE, "resync: %s", hipGetErrorString(e));
+    for (int n = 0; n < ctx->N; ++n) ctx->m[n].fresh = true;
     ctx->pend.clear();
     ctx->stale = false;
     return TF_OK;

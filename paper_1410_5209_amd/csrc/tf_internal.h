@@ -74,6 +74,8 @@ struct AccumArgs {
     const Chunk *chunks;
     const int32_t *oidx[kMaxModes - 1];  // other modes ascending, CSR order
     void *rhat;                          // residual copy of this mode (CSR order)
+    const int32_t *rperm;                // non-null (plain passes only): the
+                                         // residual of entry j is rhat[rperm[j]]
     const void *W[kMaxModes - 1];        // other modes: current slabs
     const void *S[kMaxModes - 1];        // other modes: split-start slabs
     const void *P[kMaxModes - 1];        // other modes: pending-column slabs
@@ -126,6 +128,10 @@ hipError_t init_factor(int prec, void *A, int64_t I, int K, uint64_t seed, uint6
 hipError_t residual_input_order(int prec, const int32_t *idx, const double *x, int64_t nnz,
                                 int N, const void *const *A, int K, bool zero_model,
                                 double *r_out, hipStream_t st);
+hipError_t compose_with_mode0(const int32_t *perm0, const int32_t *permn, int64_t nnz,
+                              int32_t *inv_scratch, int32_t *out, hipStream_t st);
+hipError_t gather_copy(int prec, const void *in, const int32_t *idx, int64_t nnz, void *out,
+                       hipStream_t st);
 hipError_t gather_residual(int prec, const double *r_in, const int32_t *perm, int64_t nnz,
                            void *rhat_out, hipStream_t st);
 hipError_t factor_to_f64(int prec, const void *A, int64_t n, double *out, hipStream_t st);
@@ -198,6 +204,12 @@ struct tf_ctx {
         int32_t nsplit = 0;
         std::vector<int64_t> h_rowptr;
         int32_t lane_nnz = 0, split_threshold = 0, chunk_nnz = 0;   // plan in use
+        // residual source of this mode's passes (modes >= 1): its own copy,
+        // or mode 0's copy read through pos0 (position in mode-0 order of
+        // each entry of this mode's order)
+        int32_t *pos0 = nullptr;        // nnz, built on first use
+        bool shared = false;            // the last split read mode 0's copy
+        bool fresh = true;              // own copy holds the current R-hat
     } m[tfk::kMaxModes];
 
     int64_t ld = 0;           // slab row stride (elements, 128-byte multiple)

@@ -12,7 +12,7 @@ class SparseCP:
 
     def __init__(self, dims, idx, vals, K, lam, precision="f32", reg_mode=0,
                  first_factor_zero=True, strategy=tf.TF_STRATEGY_SKEW, seed=2, stream=None,
-                 lane_nnz=2, split_threshold=4096, chunk_nnz=2048):
+                 lane_nnz=2, split_threshold=4096, chunk_nnz=2048, resid_share=tf.TF_RESID_AUTO):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("SparseCP needs a HIP GPU")
@@ -32,7 +32,7 @@ class SparseCP:
                                     first_factor_zero=1 if first_factor_zero else 0,
                                     strategy=int(strategy), seed=int(seed), stream=stream,
                                     lane_nnz=int(lane_nnz), split_threshold=int(split_threshold),
-                                    chunk_nnz=int(chunk_nnz))
+                                    chunk_nnz=int(chunk_nnz), resid_share=int(resid_share))
         self.ctx = tf.tf_init(self.dims, d_idx, d_vals, self.K, self.lam, opt)
         del d_idx, d_vals  # the library keeps its own copies
 

@@ -18,6 +18,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "tf.h")
 TF_OK, TF_E_INVALID, TF_E_NOMEM, TF_E_DEVICE, TF_E_NUMERIC, TF_E_UNSUPPORTED, TF_E_BUSY, TF_E_STATE = range(8)
 TF_PREC_F64, TF_PREC_F32, TF_PREC_BF16 = 0, 1, 2
 TF_STRATEGY_PLAIN, TF_STRATEGY_SKEW = 0, 1
+TF_RESID_AUTO, TF_RESID_OWN, TF_RESID_SHARED = 0, 1, 2
 PREC = {"f64": TF_PREC_F64, "f32": TF_PREC_F32, "bf16": TF_PREC_BF16}
 
 
@@ -26,7 +27,8 @@ class tf_options(ctypes.Structure):
                 ("reg_mode", ctypes.c_int32), ("first_factor_zero", ctypes.c_int32),
                 ("strategy", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("stream", ctypes.c_void_p), ("lane_nnz", ctypes.c_int32),
-                ("split_threshold", ctypes.c_int32), ("chunk_nnz", ctypes.c_int32)]
+                ("split_threshold", ctypes.c_int32), ("chunk_nnz", ctypes.c_int32),
+                ("resid_share", ctypes.c_int32)]
 
 
 class tf_kstats(ctypes.Structure):

@@ -22,6 +22,7 @@ def test_options_struct_matches_header_defaults():
     assert o.size == ctypes.sizeof(tf.tf_options) == 56
     assert (o.precision, o.reg_mode, o.first_factor_zero, o.strategy, o.seed) == (1, 0, 1, 1, 2)
     assert (o.lane_nnz, o.split_threshold, o.chunk_nnz) == (2, 4096, 2048)
+    assert o.resid_share == tf.TF_RESID_AUTO
 
 
 def _rowptr(counts):

@@ -99,6 +99,31 @@ def test_changing_split_width_f64():
     g.close()
 
 
+@pytest.mark.parametrize("share", ["own", "shared", "auto"])
+def test_residual_placement_f64(share):
+    """Modes 2..N keep their own R-hat or read mode 1's through a permutation;
+    widths alternate so that the automatic choice switches back and forth
+    (a mode returning to its own copy takes mode 1's R-hat first)."""
+    from paper_1410_5209_amd import tf
+    mode = {"own": tf.TF_RESID_OWN, "shared": tf.TF_RESID_SHARED, "auto": tf.TF_RESID_AUTO}[share]
+    dims, K = [40, 35, 30, 25], 24
+    note(f"residual placement f64 {share}")
+    idx, x, A = problem(17, dims, 5000, K)
+    g, o = pair(dims, idx, x, A, K, 0.2, "f64", resid_share=mode)
+    plan = [(list(range(16)), 1), ([16, 17, 18], 1), (list(range(8, 24)), 2), ([0, 5, 9, 13, 2], 1),
+            (list(range(12)), 1), ([23], 2)]
+    for cols, t_in in plan:
+        g.split(cols, t_in)
+        o.split(cols, t_in)
+        for n in range(4):
+            assert rel_max(g.factor(n), o.get_factor(n)) < 1e-10, (cols, n)
+    assert rel_max(g.residual(), o.residual()) < 1e-10
+    gl, _ = g.loss()
+    ol, _ = o.loss()
+    assert abs(gl - ol) <= 1e-9 * ol
+    g.close()
+
+
 def test_sweeps_with_random_column_orders_f64():
     dims, K, C = [80, 70, 60], 9, 4
     note("sweeps random order f64")
