@@ -15,9 +15,11 @@
 // k_solve_wide: half a wavefront per row: (B + lambda_i I) a = c in FP64 by
 //   Cholesky (text after Theorem 1), M = L L^T computed in place with lane i
 //   holding row i of the lower triangle in registers.  Step j: lane j forms
-//   L(j, j) and y_j; lanes i > j form L(i, j) and publish it in LDS, then
-//   every lane updates its row.  Back substitution L^T a = y: lane k
-//   publishes row k of L and a_k.  a goes to the W segment of the mode's slab.
+//   1 / L(j, j) and y_j, which reach the half by lane reads; lanes i > j form
+//   L(i, j) and store it as column j of L in LDS, from where every lane
+//   updates its row.  Back substitution L^T a = y: lane i takes column i of L
+//   from LDS, and each a_k reaches the half by lane reads.  a goes to the W
+//   segment of the mode's slab.
 #pragma once
 
 #include "dev_common.h"
@@ -175,6 +177,16 @@ __global__ __launch_bounds__(256) void k_accum_wide(AccumArgs a)
     }
 }
 
+// A double from lane k of each 32-lane half, returned to every lane of that
+// half (k is a compile-time lane number in the callers).
+__device__ __forceinline__ double half_bcast(double v, int k, int half)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const int lo0 = __builtin_amdgcn_readlane(lo, k), hi0 = __builtin_amdgcn_readlane(hi, k);
+    const int lo1 = __builtin_amdgcn_readlane(lo, k + 32), hi1 = __builtin_amdgcn_readlane(hi, k + 32);
+    return half ? __hiloint2double(hi1, lo1) : __hiloint2double(hi0, lo0);
+}
+
 // 1 / sqrt(d) for d > 0: hardware estimate, then two steps of Newton's
 // iteration r <- r (3 - d r^2) / 2 (each roughly doubles the correct bits).
 __device__ __forceinline__ double rsqrt_nr(double d)
@@ -191,8 +203,11 @@ __global__ __launch_bounds__(256) void k_solve_wide(SolveArgs a)
     using TS = typename Types<PREC>::TS;
     constexpr int NEP = gram_stride(WCP);
     constexpr int NV = NEP / 4;
-    __shared__ float4 rec[8][NV];           // the block's eight Gram records
-    __shared__ double pub[8][WCP + 2];      // per row: published column / row of L, [WCP..] scalars
+    constexpr int LT = WCP * (WCP - 1) / 2;     // strictly lower entries of L
+    static_assert(NEP * sizeof(float) <= LT * sizeof(double), "record must fit the L area");
+    // per row: first the staged Gram record, then the columns of L below the
+    // diagonal (column j at colofs(j), rows j+1..31)
+    __shared__ __align__(16) double lt[8][LT];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int half = lane >> 5;
@@ -200,23 +215,26 @@ __global__ __launch_bounds__(256) void k_solve_wide(SolveArgs a)
     const int slot = 2 * wave + half;
     const int64_t row0 = (int64_t)blockIdx.x * 8 + 2 * wave;
     const int64_t row = row0 + half;
+    auto colofs = [](int j) { return j * (WCP - 1) - j * (j - 1) / 2; };
 
     // the wavefront's two records, coalesced, into LDS
     const float4 *gsrc = reinterpret_cast<const float4 *>(a.gram);
     for (int v = lane; v < 2 * NV; v += 64) {
         const int r = v >= NV ? 1 : 0;
         const int q = v - r * NV;
-        if (row0 + r < a.I) rec[2 * wave + r][q] = gsrc[(row0 + r) * NV + q];
+        if (row0 + r < a.I)
+            reinterpret_cast<float4 *>(lt[2 * wave + r])[q] = gsrc[(row0 + r) * NV + q];
     }
     __builtin_amdgcn_wave_barrier();
 
     const bool valid = row < a.I;
     const int64_t cnt = valid ? (int64_t)a.rowptr[row + 1] - a.rowptr[row] : 0;
     const bool live = cnt > 0;
-    const float *rf = reinterpret_cast<const float *>(rec[slot]);
+    const float *rf = reinterpret_cast<const float *>(lt[slot]);
     // lane i: M(i, k) for k <= i, which is record entry (k, i) of the upper
     // triangle, and c_i; an empty or absent row solves the identity system.
-    // Slots k > i are scratch.
+    // Slots k > i are scratch until the back substitution, where they hold
+    // column i of L.
     const double lam = a.reg_mode ? a.lambda * (double)cnt : a.lambda;
     double m[WCP];
 #pragma unroll
@@ -226,8 +244,11 @@ __global__ __launch_bounds__(256) void k_solve_wide(SolveArgs a)
         if (k == i) m[k] = live ? m[k] + lam : 1.0;
     }
     double c = live ? (double)rf[WNT + i] : 0.0;
+    // the record is consumed before L overwrites it
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_wave_barrier();
 
-    double *u = pub[slot];
+    double *L = lt[slot];
     bool ok = true;
     double rinv = 1.0;
 #pragma unroll
@@ -239,45 +260,46 @@ __global__ __launch_bounds__(256) void k_solve_wide(SolveArgs a)
             rinv = rsqrt_nr(dd);        // 1 / L(j, j)
             m[j] = dd * rinv;
             c *= rinv;                  // y_j of L y = c
-            u[WCP] = rinv;
-            u[WCP + 1] = c;
         }
-        __builtin_amdgcn_wave_barrier();
-        const double dj = u[WCP], yj = u[WCP + 1];
+        const double dj = half_bcast(rinv, j, half), yj = half_bcast(c, j, half);
         double lij = 0.0;
         if (i > j) {
             lij = m[j] * dj;            // L(i, j)
             m[j] = lij;
             c -= lij * yj;
-            u[i] = lij;
+            L[colofs(j) + i - j - 1] = lij;
         }
         __builtin_amdgcn_wave_barrier();
         // M(i, k) -= L(i, j) L(k, j); lanes i <= j have lij = 0 and only
-        // scratch slots at k > j.  The empty asm pins each update to this
-        // step (left to itself the compiler defers them and keeps the
-        // published column live in registers across steps).
-        double col[WCP];
+        // scratch slots at k > j.  The column is read eight values at a time
+        // (the memory clobber keeps later groups' reads from being hoisted)
+        // and each update is pinned to this step by an empty asm (left to
+        // itself the compiler defers the updates and keeps columns of
+        // several steps live in registers).
 #pragma unroll
-        for (int k = j + 1; k < WCP; ++k) col[k] = u[k];
+        for (int k0 = j + 1; k0 < WCP; k0 += 8) {
+            double col[8];
 #pragma unroll
-        for (int k = j + 1; k < WCP; ++k) {
-            m[k] -= lij * col[k];
-            asm volatile("" : "+v"(m[k]));
+            for (int k = k0; k < k0 + 8 && k < WCP; ++k) col[k - k0] = L[colofs(j) + k - j - 1];
+#pragma unroll
+            for (int k = k0; k < k0 + 8 && k < WCP; ++k) {
+                m[k] -= lij * col[k - k0];
+                asm volatile("" : "+v"(m[k]));
+            }
+            asm volatile("" ::: "memory");
         }
-        __builtin_amdgcn_wave_barrier();
     }
-    // L^T a = y, last unknown first
+    __builtin_amdgcn_wave_barrier();
+    // column i of L into the scratch slots, then L^T a = y, last unknown first
+    const int ci = colofs(i) - i - 1;
+#pragma unroll
+    for (int k = 1; k < WCP; ++k)
+        if (k > i) m[k] = L[ci + k];
 #pragma unroll
     for (int k = WCP - 1; k >= 0; --k) {
-        if (i == k) {
-            c *= rinv;                  // a_k
-#pragma unroll
-            for (int t = 0; t < k; ++t) u[t] = m[t];
-            u[WCP + 1] = c;
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (i < k) c -= u[i] * u[WCP + 1];
-        __builtin_amdgcn_wave_barrier();
+        if (i == k) c *= rinv;          // a_k
+        const double ak = half_bcast(c, k, half);
+        if (i < k) c -= m[k] * ak;
     }
 
     const unsigned long long bad = __ballot(!ok);
