@@ -37,8 +37,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "nnz·C updates/s per SALS/CDTF sweep, % HBM roofline; fold-in p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_1410_5209_amd/csrc/k_rows.inc.h", "paper_1410_5209_amd/csrc/dev_common.h",
-                  "paper_1410_5209_amd/csrc/tf_internal.h"]
+KERNEL_SOURCES = ["paper_1410_5209_amd/csrc/k_rows.inc.h", "paper_1410_5209_amd/csrc/k_rows_wide.inc.h",
+                  "paper_1410_5209_amd/csrc/dev_common.h", "paper_1410_5209_amd/csrc/tf_internal.h",
+                  "paper_1410_5209_amd/csrc/tf_api.hip"]
 
 
 def kernel_source_hash() -> str:
@@ -321,9 +322,15 @@ def main():
                    "T_in": w.T_in, "lambda": w.lam, "precision": w.prec,
                    "strategy": "skew" if args.strategy == 1 else "plain",
                    "parallelism": "single-gpu"},
-        "roofline": {"bound": "hbm", "kernel": "k_accum (gather + Gram accumulation)",
+        "roofline": {"bound": "hbm",
+                     "kernel": ("k_accum_wide (gather + MFMA Gram accumulation)" if C > 16 else
+                                "k_accum (gather + Gram accumulation)"),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_gbs": (traffic / 1e6 / avg_ms) if traffic else None,
+                     "note": "achieved = algorithmic bytes (each gathered factor row and each "
+                             "residual counted at its size, no cache credit) / kernel time; "
+                             "traffic = DRAM-side bytes per launch from FETCH_SIZE + WRITE_SIZE",
                      "launches": ks.launches, "avg_launch_ms": avg_ms,
                      "alg_bytes_per_launch": bytes_per_launch,
                      "kernel_share_of_sweep": ks.total_ms / (dt * 1000.0)},

@@ -31,14 +31,27 @@ constexpr int WNT = WCP * (WCP + 1) / 2;      // 528 Gram entries (upper)
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// Column c of a factor-row segment.  BF16: the lane pair (2k, 2k+1) reads
-// the same aligned 4-byte word and keeps its half (sub-dword loads ran at
-// half the rate of dword loads here).
-__device__ __forceinline__ float load_col(const float *row, int c) { return row[c]; }
-__device__ __forceinline__ float load_col(const bf16 *row, int c)
+// Column c of a factor-row segment, in two steps so that a group's loads
+// are all issued before any result is used: load_raw fetches the 4-byte word
+// holding the column (BF16: the lane pair 2k, 2k+1 shares one word),
+// col_value turns it into the column's FP32 value.
+__device__ __forceinline__ uint32_t load_raw(const float *row, int c)
 {
-    const uint32_t x = reinterpret_cast<const uint32_t *>(row)[c >> 1];
+    return __float_as_uint(row[c]);
+}
+__device__ __forceinline__ uint32_t load_raw(const bf16 *row, int c)
+{
+    return reinterpret_cast<const uint32_t *>(row)[c >> 1];
+}
+template <typename TS> __device__ __forceinline__ float col_value(uint32_t x, int c);
+template <> __device__ __forceinline__ float col_value<float>(uint32_t x, int) { return __uint_as_float(x); }
+template <> __device__ __forceinline__ float col_value<bf16>(uint32_t x, int c)
+{
     return __uint_as_float((c & 1) ? (x & 0xffff0000u) : (x << 16));
+}
+template <typename TS> __device__ __forceinline__ float load_col(const TS *row, int c)
+{
+    return col_value<TS>(load_raw(row, c), c);
 }
 
 // Sum over each 32-lane half: quad swaps, half-row and row mirrors, then the
@@ -110,7 +123,8 @@ __global__ __launch_bounds__(256) void k_accum_wide(AccumArgs a)
             float rnew = 0.f;
             const int nstep = (int)((end - s0 + 1) / 2 < 32 ? (end - s0 + 1) / 2 : 32);
             for (int u0 = 0; u0 < nstep; u0 += GS) {
-                float w[GS][NO], pv[GS][NO], sv[GS][NO], rq[GS];
+                uint32_t w[GS][NO], pv[GS][NO], sv[GS][NO];
+                float rq[GS];
                 bool val[GS];
 #pragma unroll
                 for (int q = 0; q < GS; ++q) {
@@ -122,22 +136,25 @@ __global__ __launch_bounds__(256) void k_accum_wide(AccumArgs a)
                     rq[q] = __shfl(brh, src, 64);
 #pragma unroll
                     for (int l = 0; l < NO; ++l) {
-                        w[q][l] = pv[q][l] = sv[q][l] = 0.f;
+                        w[q][l] = pv[q][l] = sv[q][l] = 0u;
                         if (val[q]) {
                             const int64_t off = (int64_t)ii[l] * ld;
-                            w[q][l] = load_col(reinterpret_cast<const TS *>(a.W[l]) + off, c);
+                            w[q][l] = load_raw(reinterpret_cast<const TS *>(a.W[l]) + off, c);
                             if constexpr (FIRST) {
-                                if (a.has_pend) pv[q][l] = load_col(reinterpret_cast<const TS *>(a.P[l]) + off, c);
-                                if (a.before[l]) sv[q][l] = load_col(reinterpret_cast<const TS *>(a.S[l]) + off, c);
+                                if (a.has_pend) pv[q][l] = load_raw(reinterpret_cast<const TS *>(a.P[l]) + off, c);
+                                if (a.before[l]) sv[q][l] = load_raw(reinterpret_cast<const TS *>(a.S[l]) + off, c);
                             }
                         }
                     }
                 }
 #pragma unroll
                 for (int q = 0; q < GS; ++q) {
-                    float p = val[q] ? w[q][0] : 0.f;
+                    float wv[NO];
 #pragma unroll
-                    for (int l = 1; l < NO; ++l) p *= w[q][l];
+                    for (int l = 0; l < NO; ++l) wv[l] = col_value<TS>(w[q][l], c);
+                    float p = val[q] ? wv[0] : 0.f;
+#pragma unroll
+                    for (int l = 1; l < NO; ++l) p *= wv[l];
                     float r = rq[q];
                     if constexpr (FIRST) {
                         // R-hat of this split: the previous split's columns
@@ -145,8 +162,8 @@ __global__ __launch_bounds__(256) void k_accum_wide(AccumArgs a)
                         float tp = val[q] ? own_p : 0.f, ts = val[q] ? own_s : 0.f;
 #pragma unroll
                         for (int l = 0; l < NO; ++l) {
-                            tp *= pv[q][l];
-                            ts *= a.before[l] ? sv[q][l] : w[q][l];
+                            tp *= col_value<TS>(pv[q][l], c);
+                            ts *= a.before[l] ? col_value<TS>(sv[q][l], c) : wv[l];
                         }
                         r = (r - half_sum(tp)) + half_sum(ts);
                         const float rh0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r), 0));

@@ -47,13 +47,25 @@ def _is_copy(name):
     return "copyBuffer" in name
 
 
-def counter_bytes(path):
-    """(kernel KiB per launch mean, copy KiB mean, launches) from one counter CSV."""
+def counter_bytes(path, last=0):
+    """(kernel KiB per launch mean, copy KiB mean, launches) from one counter CSV;
+    with last > 0 only the last `last` accumulation launches (the timed sweeps,
+    after any tuning trials) are averaged."""
     rows = _counter_rows(path)
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
     acc = _per_kernel(rows, _is_accum)
-    cp = _per_kernel(rows, _is_copy)
-    # the 1 GiB copies are the largest copyBuffer dispatches
-    cp = sorted(cp)[-3:] if cp else []
+    if last > 0:
+        acc = acc[-last:]
+    # the calibration: bench.py --calibrate-copy runs three 1 GiB copies back
+    # to back, i.e. three consecutive copy dispatches with equal readings
+    cps = [(int(r["Dispatch_Id"]), float(r["Counter_Value"])) for r in rows if _is_copy(r["Kernel_Name"])]
+    cp = []
+    for q in range(len(cps) - 2):
+        ids = [cps[q + t][0] for t in range(3)]
+        vals = [cps[q + t][1] for t in range(3)]
+        if ids == [ids[0], ids[0] + 1, ids[0] + 2] and min(vals) > 0 and max(vals) / min(vals) < 1.01:
+            cp = vals
+            break
     return (statistics.mean(acc) if acc else None, statistics.mean(cp) if cp else None, len(acc))
 
 
@@ -75,13 +87,15 @@ def main():
     ap.add_argument("--fetch-cmd", default="")
     ap.add_argument("--write-cmd", default="")
     ap.add_argument("--bench-json", default=None, help="bench.py output line of the same build")
+    ap.add_argument("--last", type=int, default=0,
+                    help="average only the last N accumulation launches of each counter run")
     args = ap.parse_args()
 
     from bench import kernel_source_hash
 
     stats = kernel_stats(args.stats)
     total = sum(float(r["TotalDurationNs"]) for r in stats)
-    lines = [f"# k_accum on {args.workload}", "",
+    lines = [f"# Row-accumulation kernels on {args.workload}", "",
              "Per-kernel durations from `rocprofv3 --kernel-trace --stats` (times in microseconds).",
              "", f"Command: `{args.stats_cmd}`", "",
              "| kernel | calls | avg us | min us | max us | share |", "|---|---|---|---|---|---|"]
@@ -92,12 +106,12 @@ def main():
     acc = [r for r in stats if "k_accum" in r["Name"]]
     calls = sum(int(r["Calls"]) for r in acc)
     avg_us = sum(float(r["TotalDurationNs"]) for r in acc) / max(calls, 1) / 1e3
-    lines += ["", f"All k_accum launches: {calls} calls, average {avg_us:.1f} us per launch."]
+    lines += ["", f"All accumulation launches (k_accum*): {calls} calls, average {avg_us:.1f} us per launch."]
 
     traffic = None
     if args.fetch and args.write:
-        fk, fc, nf = counter_bytes(args.fetch)
-        wk, wc, nw = counter_bytes(args.write)
+        fk, fc, nf = counter_bytes(args.fetch, args.last)
+        wk, wc, nw = counter_bytes(args.write, args.last)
         ffac = (COPY_BYTES / 1024) / fc if fc else 1.0
         wfac = (COPY_BYTES / 1024) / wc if wc else 1.0
         fbytes = fk * 1024 * ffac
@@ -107,13 +121,14 @@ def main():
                    "bytes_per_launch": fbytes + wbytes, "launches_sampled": nf,
                    "copy_fetch_kib": fc, "copy_write_kib": wc,
                    "fetch_scale": ffac, "write_scale": wfac}
-        lines += ["", "## HBM-side traffic of k_accum (rocprofv3 --pmc)", "",
+        lines += ["", "## HBM-side traffic of the accumulation kernels (rocprofv3 --pmc)", "",
                   f"FETCH_SIZE command: `{args.fetch_cmd}`", "",
                   f"WRITE_SIZE command: `{args.write_cmd}`", "",
                   "A 1 GiB device copy (`__amd_rocclr_copyBuffer`) in the same runs calibrates the "
                   f"counters: FETCH_SIZE read {fc:.0f} KiB (scale {ffac:.4f}), WRITE_SIZE read "
                   f"{wc:.0f} KiB (scale {wfac:.4f}) for 1048576 KiB moved.", "",
-                  f"k_accum per launch (mean of {nf} launches): fetch {fbytes/1e9:.3f} GB, "
+                  f"per accumulation launch (mean of the last {nf} launches, the timed sweep): "
+                  f"fetch {fbytes/1e9:.3f} GB, "
                   f"write {wbytes/1e9:.3f} GB, total {(fbytes+wbytes)/1e9:.3f} GB."]
         tpath = os.path.join(ROOT, "profiles", f"k_accum_{args.workload}_traffic.json")
         with open(tpath, "w") as f:
@@ -124,7 +139,7 @@ def main():
         rf = b["roofline"]
         lines += ["", "## bench.py line of the same build", "",
                   f"value {b['value']:.4g} {b['unit']}, {b['ms_per_step']:.1f} ms per sweep; "
-                  f"k_accum average launch {rf['avg_launch_ms']:.3f} ms (HIP events), "
+                  f"accumulation kernels: average launch {rf['avg_launch_ms']:.3f} ms (HIP events), "
                   f"{rf['alg_bytes_per_launch']/1e9:.3f} GB algorithmic per launch, "
                   f"achieved {rf['achieved']:.0f} GB/s = {100*rf['frac']:.1f}% of 8 TB/s."]
     out = os.path.join(ROOT, "profiles", f"k_accum_{args.workload}.md")
