@@ -242,20 +242,22 @@ int row_lines(const tf_ctx *c, int CP, bool p, bool s)
 // Whether mode n (>= 1) reads mode 0's residual copy in this split: the
 // option, or (auto) the smaller count of random line requests per entry
 // over the split's T_in passes.  Own copy: the first pass gathers W, P (when
-// columns are pending) and S (modes already updated) of every other mode.
-// Shared: W only, plus one residual read per pass.
+// columns are pending) and S (modes already updated) of every other mode,
+// and is charged one line more for writing the residual back and for the
+// boundary arithmetic (measured: a first pass costs more than its gathers).
+// Shared: W only, plus one residual read per pass.  Ties go to shared.
 bool want_shared(const tf_ctx *c, int n, int CP, int npend, int T_in)
 {
     if (n == 0 || c->opt.resid_share == TF_RESID_OWN) return false;
     if (c->opt.resid_share == TF_RESID_SHARED) return true;
-    int own = 0, shared = T_in;
+    int own = 1, shared = T_in;
     for (int l = 0; l < c->N; ++l) {
         if (l == n) continue;
         const int w = row_lines(c, CP, false, false);
         own += row_lines(c, CP, npend > 0, l < n) + (T_in - 1) * w;
         shared += T_in * w;
     }
-    return shared < own;
+    return shared <= own;
 }
 
 // pos0 of mode n: position in mode 0's order of each entry of mode n's order.
