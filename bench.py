@@ -67,7 +67,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, scale=4, C=None):
+def cpu_baseline(w, scale=4, C=None, reg_mode=0):
     """The oracle as it stands, on one split of the same recipe at 1/scale size
     (mode lengths and entries both divided by `scale`, so every row keeps the
     full workload's mean length; K, C, T_in, lambda unchanged)."""
@@ -76,7 +76,7 @@ def cpu_baseline(w, scale=4, C=None):
     r = w.replica(w.I // scale, w.nnz // scale, C=C or w.C)
     idx, x = synth.make_tensor(r)[:2]
     t0 = time.perf_counter()
-    o = orc.Oracle([r.I] * r.N, idx, x, r.K, r.lam)
+    o = orc.Oracle(r.dims, idx, x, r.K, r.lam, reg_mode)
     o.init_factors(2, True)
     t_setup = time.perf_counter() - t0
     cols = list(range(min(r.C, r.K)))
@@ -88,7 +88,7 @@ def cpu_baseline(w, scale=4, C=None):
     return {"value": updates / dt, "unit": "nnz·C updates/s", "cores": orc.get_threads(),
             "kind": "oracle",
             "sample": f"one split (C={len(cols)}, T_in={r.T_in}) of the same recipe at 1/{scale} size "
-                      f"(I={r.I} per mode, {idx.shape[0]} entries, K={r.K}): {updates} updates in "
+                      f"(mode lengths {r.dims}, {idx.shape[0]} entries, K={r.K}): {updates} updates in "
                       f"{dt:.2f} s; setup {t_setup:.1f} s untimed"}
 
 
@@ -103,7 +103,7 @@ def serve_bench(m, w, rates, seconds, streams, max_batch):
     import synth
     from paper_1410_5209_amd import tf
 
-    dims = [w.I] * w.N
+    dims = w.dims
     out = []
     for method, name in ((tf.TF_FOLDIN_FULL, "full-rank"), (tf.TF_FOLDIN_CDTF, "cdtf x3")):
         srv = tf.tf_serve_open(m.ctx, tf.tf_serve_default_options(
@@ -139,8 +139,7 @@ def serve_bench(m, w, rates, seconds, streams, max_batch):
 def precision_compare(w, data, sweeps):
     """Held-out test RMSE and sweep time of the plain FP32 form (one wavefront
     per row, default tiles) against the batched forms (skew-aware plan, tuned
-    row tiles) in FP32 and BF16 storage, at the workload's C and, for BF16, at
-    a tuned C.  Every form trains from the same seeded start for `sweeps`
+    row tiles) in FP32 and BF16 storage, at the workload's C and at a tuned C.  Every form trains from the same seeded start for `sweeps`
     sweeps; times are the median sweep."""
     import numpy as np
     import torch
@@ -149,10 +148,11 @@ def precision_compare(w, data, sweeps):
     from paper_1410_5209_amd.model import SparseCP
 
     idx, x, idx_t, x_t = data
-    dims = [w.I] * w.N
+    dims = w.dims
     forms = (("fp32-plain", "f32", tf.TF_STRATEGY_PLAIN, None),
              ("fp32-batched", "f32", tf.TF_STRATEGY_SKEW, [w.C]),
              ("bf16-batched", "bf16", tf.TF_STRATEGY_SKEW, [w.C]),
+             ("fp32-batched-tunedC", "f32", tf.TF_STRATEGY_SKEW, [w.C, 16, 32]),
              ("bf16-batched-tunedC", "bf16", tf.TF_STRATEGY_SKEW, [w.C, 16, 32]))
     out = {}
     for name, prec, strat, cands in forms:
@@ -185,6 +185,45 @@ def precision_compare(w, data, sweeps):
     return out
 
 
+def c_tin_sweep(w, data, cs, tins, sweeps):
+    """The split width C and inner-iteration count T_in varied on one
+    workload: for each pair, a fresh model from the same seeded start (row
+    tiles tuned for that C, not timed), `sweeps` timed sweeps, then the
+    regularised loss and training RMSE.  Columns above 32 per split are not
+    run (the kernels take at most 32)."""
+    import numpy as np
+    import torch
+
+    from paper_1410_5209_amd.model import SparseCP
+
+    idx, x = data[0], data[1]
+    out = []
+    for T_in in tins:
+        for C in cs:
+            if C > w.K or C > 32:
+                continue
+            m = SparseCP(w.dims, idx, x, w.K, w.lam, precision=w.prec)
+            m.autotune(T_in, [C], tune_tiles=True)
+            times = []
+            for _ in range(sweeps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                m.sweep(C, T_in)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            loss, rmse = m.loss()
+            med = float(np.median(times))
+            rec = {"C": C, "T_in": T_in, "median_sweep_ms": 1e3 * med,
+                   "upd_per_s": len(x) * w.K * T_in * w.N / med,
+                   "sweeps": sweeps, "loss": loss, "train_rmse": rmse}
+            out.append(rec)
+            log(f"C={C} T_in={T_in}: {1e3 * med:.1f} ms/sweep, train RMSE {rmse:.5f}")
+            m.close()
+            del m
+            torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,6 +240,13 @@ def main():
                     help="oracle sample at 1/scale size (default 4; 40 for the 5-way workload)")
     ap.add_argument("--no-serve", action="store_true", help="skip the fold-in serving runs")
     ap.add_argument("--no-tune", action="store_true", help="use the default row tiles")
+    ap.add_argument("--reg-mode", type=int, default=0, choices=[0, 1],
+                    help="1: weighted lambda (lambda times the row's entry count)")
+    ap.add_argument("--col-order", default="fixed", choices=["fixed", "random"],
+                    help="random: a seeded column permutation per sweep")
+    ap.add_argument("--c-sweep", default=None,
+                    help="comma-separated C values: time and accuracy per (C, T_in) pair")
+    ap.add_argument("--tin-sweep", default="1", help="comma-separated T_in values for --c-sweep")
     ap.add_argument("--precision-compare", action="store_true",
                     help="with a held-out workload: BF16 vs FP32 test RMSE and sweep time")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
@@ -223,13 +269,19 @@ def main():
     from paper_1410_5209_amd.model import SparseCP
 
     w = synth.WORKLOADS[args.workload]
-    dims = [w.I] * w.N
+    dims = w.dims
     t0 = time.perf_counter()
     data = synth.make_tensor(w)
     idx, x = data[0], data[1]
     log(f"generated {idx.shape[0]} entries in {time.perf_counter() - t0:.1f} s")
 
     torch.cuda.set_device(0)
+    if args.c_sweep:
+        res = c_tin_sweep(w, data, [int(c) for c in args.c_sweep.split(",")],
+                          [int(t) for t in args.tin_sweep.split(",")], w.sweeps)
+        print(json.dumps({"workload": w.name, "dims": w.dims, "nnz": int(len(data[1])), "K": w.K,
+                          "lambda": w.lam, "c_tin_sweep": res}), flush=True)
+        return
     if args.precision_compare:
         if len(data) != 4:
             raise SystemExit("--precision-compare needs a workload with a held-out split")
@@ -238,7 +290,7 @@ def main():
         return
     t0 = time.perf_counter()
     m = SparseCP(dims, idx, x, w.K, w.lam, precision=w.prec, strategy=args.strategy,
-                 lane_nnz=args.lane_nnz)
+                 lane_nnz=args.lane_nnz, reg_mode=args.reg_mode)
     torch.cuda.synchronize()
     log(f"tf_init {time.perf_counter() - t0:.1f} s")
 
@@ -264,8 +316,15 @@ def main():
                 "tune_ms": r.tune_ms}
         log(f"autotune: C={C} ({r.tune_ms:.0f} ms)")
 
-    for s in range(args.warmup):
+    def one_sweep(s):
+        # random order: the columns of every sweep are drawn without
+        # replacement (Algorithm 1), as a seeded permutation per sweep
+        if args.col_order == "random":
+            m.set_col_order(synth.column_order(synth.SEED_ORDER, s, w.K))
         m.sweep(C, w.T_in)
+
+    for s in range(args.warmup):
+        one_sweep(s)
         log(f"warmup sweep {s} done")
     torch.cuda.synchronize()
 
@@ -273,7 +332,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
-        m.sweep(C, w.T_in)
+        one_sweep(args.warmup + s)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ks = m.profile_read()
@@ -302,7 +361,7 @@ def main():
         log("timing the oracle on one split")
         del idx, x
         scale = args.cpu_scale or (40 if w.N == 5 else 4)
-        cpu = cpu_baseline(w, scale, C)
+        cpu = cpu_baseline(w, scale, C, args.reg_mode)
 
     out = {
         "metric": METRIC,
@@ -317,9 +376,10 @@ def main():
         "vs_baseline": None,
         "dtype": {"f64": "f64", "f32": "f32", "bf16": "bf16-storage/f32"}[w.prec],
         "data": "synthetic",
-        "config": {"workload": w.name, "N": w.N, "I": w.I, "nnz": nnz, "K": w.K, "C": C,
+        "config": {"workload": w.name, "N": w.N, "dims": w.dims, "nnz": nnz, "K": w.K, "C": C,
                    "autotune": tune,
                    "T_in": w.T_in, "lambda": w.lam, "precision": w.prec,
+                   "reg_mode": args.reg_mode, "col_order": args.col_order,
                    "strategy": "skew" if args.strategy == 1 else "plain",
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm",

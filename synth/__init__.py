@@ -168,11 +168,19 @@ class Workload:
     sweeps: int
     prec: str           # "f64" | "f32" | "bf16"
     test_frac: float = 0.0
+    shape: tuple = ()   # mode lengths when they differ (else N modes of length I)
+
+    @property
+    def dims(self):
+        return [int(d) for d in self.shape] if self.shape else [self.I] * self.N
 
     def replica(self, I, nnz, K=None, C=None, name=None):
-        """Same recipe at a reduced size (for the oracle)."""
+        """Same recipe at a reduced size (for the oracle): every mode length
+        scaled by I / self.I (at least 1), the entries to nnz."""
+        f = I / self.I
+        shape = tuple(max(1, int(round(d * f))) for d in self.shape) if self.shape else ()
         return replace(self, I=int(I), nnz=int(nnz), K=int(K or self.K), C=int(C or self.C),
-                       name=name or f"{self.name}@I{I}_nnz{nnz}")
+                       shape=shape, name=name or f"{self.name}@I{I}_nnz{nnz}")
 
 
 WORKLOADS = {
@@ -188,6 +196,16 @@ WORKLOADS = {
     # the 3-way SALS workload with BF16 factors and a 1% held-out test split
     "sals-3way-1m-bf16": Workload("sals-3way-1m-bf16", 3, 1_000_000, 100_000_000, "uniform", 0.0,
                                   "distinct", 20, 1, 0.25, 100, 1.0, 10, 2, 10, "bf16", 0.01),
+    # shape-only stand-ins for the paper's real tensors (Table 4): the mode
+    # lengths, entry counts, K and lambda of its Netflix_3 and Yahoo-music_4
+    # runs, with uniform distinct indices and rating-like values in [1, 5]
+    # (rank-20 truth + N(0, 0.25^2)); none of the datasets' content
+    "netflix3-shape-fp32": Workload("netflix3-shape-fp32", 3, 2_649_429, 99_072_112, "uniform", 0.0,
+                                    "distinct", 20, 1, 0.25, 40, 0.02, 10, 1, 3, "f32", 0.0,
+                                    (2_649_429, 17_770, 74)),
+    "yahoo4-shape-fp32": Workload("yahoo4-shape-fp32", 4, 1_000_990, 252_800_275, "uniform", 0.0,
+                                  "distinct", 20, 1, 0.25, 80, 1.0, 10, 1, 3, "f32", 0.0,
+                                  (1_000_990, 624_961, 133, 24)),
 }
 
 
@@ -195,7 +213,7 @@ def make_tensor(w: Workload, seed=SEED_DATA):
     """Index tuples (nnz x N int32) and values (nnz float64) of a workload.
 
     With test_frac > 0 also returns the held-out split: (idx, x, idx_test, x_test)."""
-    dims = [w.I] * w.N
+    dims = w.dims
     idx = tuples(seed, dims, w.nnz, w.dist, w.zipf_s, w.dedupe)
     x = values(seed, dims, idx, w.R, w.scale, w.sigma)
     if w.test_frac > 0:

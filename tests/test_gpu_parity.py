@@ -302,8 +302,8 @@ def test_library_init_draws_splitmix_factors():
     (5, [400, 300, 300, 200, 200], 40000, "zipf"),
 ])
 def test_wide_split_parity_f32(N, dims, nnz, dist):
-    """C = 32 (one wavefront per row, 4x4 Gram blocks per lane), then a split of
-    8 columns whose pending 32 columns exceed that kernel's width."""
+    """C = 32 (half a wavefront per entry, Gram on the matrix cores), then a
+    split of 8 columns whose pending 32 columns exceed that kernel's width."""
     K = 40
     note(f"wide f32 N={N} dims={dims} dist={dist}")
     idx, x, A = problem(200 + N, dims, nnz, K, dist=dist,
@@ -330,6 +330,43 @@ def test_wide_sweep_bf16_and_t_in_2():
     gl, gr = g.loss()
     ol, orr = o.loss()
     assert abs(gr - orr) <= 5e-3 * orr and abs(gl - ol) <= 1e-2 * ol
+    g.close()
+
+
+@pytest.mark.parametrize("C,T_in", [(1, 1), (5, 2), (8, 1)])
+def test_short_mode_shape_f64(C, T_in):
+    """The aspect of the paper's Netflix_3 tensor (one long mode, one very
+    short one): the 7 rows of mode 3 hold ~8.6k entries each and are cut into
+    chunks whose partial Grams are summed in a fixed order."""
+    dims, K = [3000, 200, 7], 8
+    note(f"short-mode shape f64 C={C} T_in={T_in}")
+    idx, x, A = problem(41, dims, 60000, K)
+    g, o = pair(dims, idx, x, A, K, 0.02, "f64", split_threshold=1024, chunk_nnz=512)
+    g.sweep(C, T_in)
+    o.sweep(C, T_in)
+    for n in range(3):
+        assert rel_max(g.factor(n), o.get_factor(n)) < 1e-10, n
+    gl, _ = g.loss()
+    ol, _ = o.loss()
+    assert abs(gl - ol) <= 1e-9 * ol
+    g.close()
+
+
+def test_four_mode_short_tail_shape_wide_f32():
+    """The aspect of the paper's Yahoo-music_4 tensor (two long modes, two
+    short ones) at K = 40, C = 20: the split runs at 32 columns with zero
+    padding on the wide kernel, with chunked long rows in modes 3 and 4."""
+    dims, K = [2000, 1500, 20, 6], 40
+    note("four-mode short tail wide f32")
+    idx, x, A = problem(42, dims, 80000, K)
+    g, o = pair(dims, idx, x, A, K, 1.0, "f32", split_threshold=2048, chunk_nnz=1024)
+    g.sweep(20, 1)
+    o.sweep(20, 1)
+    gl, gr = g.loss()
+    ol, orr = o.loss()
+    assert abs(gl - ol) <= 1e-4 * ol and abs(gr - orr) <= 1e-4 * orr, (gl, ol)
+    for n in range(4):
+        assert rel_max(g.factor(n), o.get_factor(n)) < 1e-3, n
     g.close()
 
 
