@@ -139,8 +139,9 @@ def serve_bench(m, w, rates, seconds, streams, max_batch):
 def precision_compare(w, data, sweeps):
     """Held-out test RMSE and sweep time of the plain FP32 form (one wavefront
     per row, default tiles) against the batched forms (skew-aware plan, tuned
-    row tiles) in FP32 and BF16 storage, at the workload's C and at a tuned C.  Every form trains from the same seeded start for `sweeps`
-    sweeps; times are the median sweep."""
+    row tiles) in FP32 and BF16 storage, at the workload's C and at a tuned C.
+    Every form trains from the same seeded start for `sweeps` sweeps; times
+    are the median sweep."""
     import numpy as np
     import torch
 

@@ -37,14 +37,23 @@ size_t ta_bytes(int prec) { return prec == P_F64 ? 8 : 4; }
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// Device bytes a batch needs (arena layout below).
+// Upper bound on the chunks of a batch (each request: ceil(m / chunk)).
+int64_t max_chunks(int64_t nreq, int64_t total) { return nreq + total / kFoldChunkEntries; }
+
+// Device bytes a batch needs (arena layout below; the first five parts are
+// staged in the same layout in pinned memory and copied in one transfer).
 size_t batch_bytes(int N, int K, int prec, int method, int64_t nreq, int64_t total)
 {
+    (void)method;
+    const int64_t nc = fold_uses_gram(K) ? max_chunks(nreq, total) : 0;
     size_t b = align256((size_t)(nreq + 1) * 8);                  // req_ptr
+    b += align256((size_t)(nreq + 1) * 4);                        // chunk_first
+    b += align256((size_t)nc * 4);                                // chunk_req
     b += align256((size_t)total * (N - 1) * 4);                   // indices
     b += align256((size_t)total * 8);                             // values
     b += align256((size_t)total * K * ta_bytes(prec));            // P
-    if (method == TF_FOLDIN_CDTF) b += align256((size_t)total * 8);  // r
+    if (!fold_uses_gram(K)) b += align256((size_t)total * 8);     // r (CDTF, large K)
+    b += align256((size_t)nc * fold_gram_stride(K) * ta_bytes(prec));  // partial Grams
     b += align256((size_t)nreq * K * 8);                          // rows
     b += 256;                                                     // flags
     return b;
@@ -52,24 +61,32 @@ size_t batch_bytes(int N, int K, int prec, int method, int64_t nreq, int64_t tot
 
 struct Arena {
     int64_t *req_ptr;
+    int32_t *chunk_first;
+    int32_t *chunk_req;
     int32_t *oidx;
     double *vals;
     void *P;
     double *r;
+    void *gpart;
     double *rows;
     unsigned long long *flags;
 };
 
 Arena carve(void *base, int N, int K, int prec, int method, int64_t nreq, int64_t total)
 {
+    (void)method;
+    const int64_t nc = fold_uses_gram(K) ? max_chunks(nreq, total) : 0;
     char *p = static_cast<char *>(base);
     Arena a{};
     a.req_ptr = reinterpret_cast<int64_t *>(p); p += align256((size_t)(nreq + 1) * 8);
+    a.chunk_first = reinterpret_cast<int32_t *>(p); p += align256((size_t)(nreq + 1) * 4);
+    a.chunk_req = reinterpret_cast<int32_t *>(p); p += align256((size_t)nc * 4);
     a.oidx = reinterpret_cast<int32_t *>(p); p += align256((size_t)total * (N - 1) * 4);
     a.vals = reinterpret_cast<double *>(p); p += align256((size_t)total * 8);
     a.P = p; p += align256((size_t)total * K * ta_bytes(prec));
     a.r = nullptr;
-    if (method == TF_FOLDIN_CDTF) { a.r = reinterpret_cast<double *>(p); p += align256((size_t)total * 8); }
+    if (!fold_uses_gram(K)) { a.r = reinterpret_cast<double *>(p); p += align256((size_t)total * 8); }
+    a.gpart = p; p += align256((size_t)nc * fold_gram_stride(K) * ta_bytes(prec));
     a.rows = reinterpret_cast<double *>(p); p += align256((size_t)nreq * K * 8);
     a.flags = reinterpret_cast<unsigned long long *>(p);
     return a;
@@ -95,6 +112,9 @@ FoldArgs fold_args(const tf_ctx *c, int mode, const Arena &ar, int64_t nreq, int
     a.sweeps = sweeps;
     a.bad = ar.flags;
     a.bad_req = ar.flags + 1;
+    a.chunk_first = ar.chunk_first;
+    a.chunk_req = ar.chunk_req;
+    a.gpart = ar.gpart;
     return a;
 }
 
@@ -161,8 +181,10 @@ namespace {
 size_t req_bytes(const tf_server *s, int64_t m)
 {
     const tf_ctx *c = s->ctx;
+    const size_t chunks = fold_uses_gram(c->K) ? (size_t)max_chunks(1, m) : 0;
     return (size_t)m * ((c->N - 1) * 4 + 8 + (size_t)c->K * ta_bytes(c->prec) +
-                        (s->o.method == TF_FOLDIN_CDTF ? 8 : 0)) + (size_t)c->K * 8 + 8 + 1024;
+                        (fold_uses_gram(c->K) ? 0 : 8)) + (size_t)c->K * 8 + 8 + 1024 +
+           chunks * (4 + (size_t)fold_gram_stride(c->K) * ta_bytes(c->prec));
 }
 
 void run_batch(tf_server *s, SSlot &slot)
@@ -172,10 +194,12 @@ void run_batch(tf_server *s, SSlot &slot)
     const int64_t nreq = (int64_t)slot.batch.size();
     int64_t total = 0;
     for (SReq *r : slot.batch) total += r->m;
-    // stage inputs in pinned memory: req_ptr | indices | values
-    int64_t *hp = reinterpret_cast<int64_t *>(slot.hin);
-    int32_t *hi = reinterpret_cast<int32_t *>(slot.hin + align256((size_t)(nreq + 1) * 8));
-    double *hv = reinterpret_cast<double *>(reinterpret_cast<char *>(hi) + align256((size_t)total * (N - 1) * 4));
+    // stage inputs in pinned memory in the arena's layout:
+    // req_ptr | chunk_first | chunk_req | indices | values
+    Arena hs = carve(slot.hin, N, K, c->prec, s->o.method, nreq, total);
+    int64_t *hp = hs.req_ptr;
+    int32_t *hi = hs.oidx;
+    double *hv = hs.vals;
     hp[0] = 0;
     int64_t off = 0;
     for (int64_t q = 0; q < nreq; ++q) {
@@ -187,11 +211,17 @@ void run_batch(tf_server *s, SSlot &slot)
         off += r->m;
         hp[q + 1] = off;
     }
+    int64_t nchunks = 0;
+    if (fold_uses_gram(K)) {
+        nchunks = fold_chunks(hp, nreq);
+        fold_chunk_tables(hp, nreq, hs.chunk_first, hs.chunk_req);
+    }
     Arena ar = carve(slot.dev, N, K, c->prec, s->o.method, nreq, total);
     const size_t in_bytes = (size_t)((char *)(hv + total) - slot.hin);
     (void)hipMemcpyAsync(ar.req_ptr, slot.hin, in_bytes, hipMemcpyHostToDevice, slot.st);
     (void)hipMemsetAsync(ar.flags, 0xff, 2 * sizeof(unsigned long long), slot.st);
     FoldArgs a = fold_args(c, s->o.mode, ar, nreq, s->o.sweeps);
+    a.nchunks = (int32_t)nchunks;
     (void)launch_fold_compute(c->prec, a, total, s->o.method, slot.st);
     (void)hipMemcpyAsync(slot.hout, ar.rows, (size_t)nreq * K * 8, hipMemcpyDeviceToHost, slot.st);
     (void)hipMemcpyAsync(slot.hflags, ar.flags, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, slot.st);
@@ -514,15 +544,26 @@ tf_status tf_foldin(tf_ctx *ctx, int32_t mode, int32_t nreq, const int64_t *h_re
     if (total > 0 && (!d_idx || !d_vals)) return fail(TF_E_INVALID, "NULL entries");
     if (ctx->stale) return fail(TF_E_STATE, "factors were set; call tf_resync first");
 
-    // workspace: req_ptr | P | r | flags (indices, values and rows are the caller's)
-    const size_t need = align256((size_t)(nreq + 1) * 8) + align256((size_t)total * ctx->K * ta_bytes(ctx->prec)) +
-                        align256((size_t)total * 8) + 256;
+    // chunk tables of the full-rank Gram (host), staged with req_ptr
+    const bool gram = fold_uses_gram(ctx->K);
+    const int64_t nchunks = gram ? fold_chunks(h_req_ptr, nreq) : 0;
+    std::vector<int32_t> h_tab((size_t)(nreq + 1 + nchunks));
+    if (gram) fold_chunk_tables(h_req_ptr, nreq, h_tab.data(), h_tab.data() + nreq + 1);
+    const size_t gs_bytes = (size_t)fold_gram_stride(ctx->K) * ta_bytes(ctx->prec);
+
+    // workspace: req_ptr | chunk tables | P | r | partial Grams | flags
+    // (indices, values and rows are the caller's)
+    const size_t need = align256((size_t)(nreq + 1) * 8) + align256(h_tab.size() * 4) +
+                        align256((size_t)total * ctx->K * ta_bytes(ctx->prec)) +
+                        align256((size_t)total * 8) + align256((size_t)nchunks * gs_bytes) + 256;
     void *ws = nullptr;
     if (hipMalloc(&ws, need) != hipSuccess) return fail(TF_E_NOMEM, "fold-in workspace");
     char *p = static_cast<char *>(ws);
     int64_t *d_ptr = reinterpret_cast<int64_t *>(p); p += align256((size_t)(nreq + 1) * 8);
+    int32_t *d_tab = reinterpret_cast<int32_t *>(p); p += align256(h_tab.size() * 4);
     void *P = p; p += align256((size_t)total * ctx->K * ta_bytes(ctx->prec));
     double *r = reinterpret_cast<double *>(p); p += align256((size_t)total * 8);
+    void *gpart = p; p += align256((size_t)nchunks * gs_bytes);
     unsigned long long *flags = reinterpret_cast<unsigned long long *>(p);
 
     FoldArgs a;
@@ -533,10 +574,14 @@ tf_status tf_foldin(tf_ctx *ctx, int32_t mode, int32_t nreq, const int64_t *h_re
     a.P = P; a.r = r; a.rows = d_rows;
     a.lambda = ctx->lambda; a.reg_mode = ctx->opt.reg_mode; a.sweeps = sweeps;
     a.bad = flags; a.bad_req = flags + 1;
+    a.chunk_first = d_tab; a.chunk_req = d_tab + nreq + 1; a.nchunks = (int32_t)nchunks;
+    a.gpart = gpart;
 
     tf_status st = TF_OK;
     unsigned long long hf[2] = {0, 0};
     hipError_t e = hipMemcpyAsync(d_ptr, h_req_ptr, (size_t)(nreq + 1) * 8, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_tab, h_tab.data(), h_tab.size() * 4, hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(flags, 0xff, 2 * sizeof(unsigned long long), ctx->stream);
     if (e == hipSuccess) e = launch_fold_validate(a, total, ctx->dims, ctx->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(hf, flags, sizeof hf, hipMemcpyDeviceToHost, ctx->stream);

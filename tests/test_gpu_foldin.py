@@ -111,6 +111,17 @@ def _serve_setup(prec="f32", K=24):
     return g, o, ptr, oidx, vals
 
 
+def _slot_bytes_full_rank(N, K, ta, nreq, total):
+    """Device bytes of a full-rank serving batch, as the library lays out its
+    slot arena: request offsets, chunk tables, indices, values, P, partial
+    Gram records (one per 256-entry chunk), rows, flags; 256-byte aligned."""
+    a = lambda b: (b + 255) & ~255
+    nc = nreq + total // 256
+    gs = (K * (K + 1) // 2 + K + 3) & ~3
+    return (a((nreq + 1) * 8) + a((nreq + 1) * 4) + a(nc * 4) + a(total * (N - 1) * 4) +
+            a(total * 8) + a(total * K * ta) + a(nc * gs * ta) + a(nreq * K * 8) + 256)
+
+
 def _submit_all(tf, srv, ptr, oidx, vals, order):
     keep, tickets = [], {}
     for q in order:
@@ -166,7 +177,7 @@ def test_serving_memory_admission_and_busy_queue():
     want = _gpu_foldin(g, 0, ptr, oidx, vals, 0)
     biggest = int(np.max(np.diff(ptr)))
     # a budget that holds one largest request per slot forces small batches
-    budget = 2 * (biggest * (2 * 4 + 8 + g.K * 4) + g.K * 8 + 4096)
+    budget = 2 * (_slot_bytes_full_rank(3, g.K, 4, 1, biggest) + 4096)
     srv = tf.tf_serve_open(g.ctx, tf.tf_serve_default_options(streams=2, mem_budget=budget,
                                                               queue_cap=8))
     keep, tickets, busy = [], {}, 0
