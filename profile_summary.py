@@ -87,6 +87,9 @@ def main():
     ap.add_argument("--fetch-cmd", default="")
     ap.add_argument("--write-cmd", default="")
     ap.add_argument("--bench-json", default=None, help="bench.py output line of the same build")
+    ap.add_argument("--tcc", default=None,
+                    help="counter_collection.csv of a `--pmc TCC_HIT_sum TCC_MISS_sum` run")
+    ap.add_argument("--tcc-cmd", default="")
     ap.add_argument("--last", type=int, default=0,
                     help="average only the last N accumulation launches of each counter run")
     args = ap.parse_args()
@@ -133,6 +136,20 @@ def main():
         tpath = os.path.join(ROOT, "profiles", f"k_accum_{args.workload}_traffic.json")
         with open(tpath, "w") as f:
             json.dump(traffic, f, indent=1)
+    if args.tcc:
+        rows = _counter_rows(args.tcc)
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        per = {}
+        for r in rows:
+            if _is_accum(r["Kernel_Name"]):
+                per.setdefault(int(r["Dispatch_Id"]), {})[r["Counter_Name"]] = float(r["Counter_Value"])
+        ids = sorted(per)[-args.last:] if args.last > 0 else sorted(per)
+        hit = sum(per[i].get("TCC_HIT_sum", 0.0) for i in ids)
+        miss = sum(per[i].get("TCC_MISS_sum", 0.0) for i in ids)
+        lines += ["", "## L2 (TCC) hit rate of the accumulation kernels", "",
+                  f"Command: `{args.tcc_cmd}`", "",
+                  f"last {len(ids)} launches (the timed sweep): {hit:.4g} hits, {miss:.4g} misses, "
+                  f"hit rate {100 * hit / max(hit + miss, 1):.1f}%."]
     if args.bench_json:
         with open(args.bench_json) as f:
             b = json.loads([l for l in f if l.startswith("{")][-1])
