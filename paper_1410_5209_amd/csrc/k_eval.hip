@@ -54,26 +54,90 @@ __device__ __forceinline__ double block_sum_256(double v)
     return s;
 }
 
-// Sum of r^2 over the mode-0 copy (per block), optionally writing r in input order.
+// Storage elements per 16-byte vector, and one vector of a row as FP64.
+template <typename TS> struct EvalVec;
+template <> struct EvalVec<double> {
+    static constexpr int W = 2;
+    __device__ static void load(const double *p, double (&o)[2])
+    {
+        const double2 t = *reinterpret_cast<const double2 *>(p);
+        o[0] = t.x; o[1] = t.y;
+    }
+};
+template <> struct EvalVec<float> {
+    static constexpr int W = 4;
+    __device__ static void load(const float *p, double (&o)[4])
+    {
+        const float4 t = *reinterpret_cast<const float4 *>(p);
+        o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w;
+    }
+};
+template <> struct EvalVec<bf16> {
+    static constexpr int W = 8;
+    __device__ static void load(const bf16 *p, double (&o)[8])
+    {
+        const uint4 t = *reinterpret_cast<const uint4 *>(p);
+        const uint32_t w[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            o[2 * h] = (double)__uint_as_float(w[h] << 16);
+            o[2 * h + 1] = (double)__uint_as_float(w[h] & 0xffff0000u);
+        }
+    }
+};
+
+// Sum of r^2 over the mode-0 copy (per block), optionally writing r in input
+// order.  The pending columns of every gathered row are read with 16-byte
+// vectors from the slab row start (the slab is laid out for their count, so
+// whole vectors stay inside the row); products and sums in FP64.
 template <int PREC>
 __global__ __launch_bounds__(256) void k_eval_resid(EvalArgs a)
 {
     using TS = typename Types<PREC>::TS;
     using TR = typename Types<PREC>::TR;
+    using V = EvalVec<TS>;
+    constexpr int MAXC = kMaxC;
+    constexpr int NV = MAXC / V::W;
     const int lane = threadIdx.x & 63;
     const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
     double se = 0.0;
     if (t < a.ntasks) {
         const Slot s = task_slot(a.tasks, a.items, a.chunks, a.rowptr, t, lane);
         const TR *rh = reinterpret_cast<const TR *>(a.rhat);
-        for (int64_t j = s.beg + s.sub; j < s.end; j += s.G) {
-            double r = (double)rh[j];
-            for (int c = 0; c < a.npend; ++c) {
-                double prod = load_f64(reinterpret_cast<const TS *>(a.Pown) + (int64_t)s.row * a.ld + c);
-                for (int l = 0; l < a.no; ++l)
-                    prod *= load_f64(reinterpret_cast<const TS *>(a.P[l]) + (int64_t)a.oidx[l][j] * a.ld + c);
-                r -= prod;
+        const int np = a.npend;
+        double own[MAXC];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double x[V::W];
+            if (v * V::W < np && s.row >= 0)
+                V::load(reinterpret_cast<const TS *>(a.Pown) + (int64_t)s.row * a.ld + v * V::W, x);
+            else {
+#pragma unroll
+                for (int e = 0; e < V::W; ++e) x[e] = 0.0;
             }
+#pragma unroll
+            for (int e = 0; e < V::W; ++e) own[v * V::W + e] = x[e];
+        }
+        for (int64_t j = s.beg + s.sub; j < s.end; j += s.G) {
+            double prod[MAXC];
+#pragma unroll
+            for (int c = 0; c < MAXC; ++c) prod[c] = own[c];
+            for (int l = 0; l < a.no; ++l) {
+                const TS *row = reinterpret_cast<const TS *>(a.P[l]) + (int64_t)a.oidx[l][j] * a.ld;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    if (v * V::W < np) {
+                        double x[V::W];
+                        V::load(row + v * V::W, x);
+#pragma unroll
+                        for (int e = 0; e < V::W; ++e) prod[v * V::W + e] *= x[e];
+                    }
+                }
+            }
+            double r = (double)rh[j];
+#pragma unroll
+            for (int c = 0; c < MAXC; ++c)
+                if (c < np) r -= prod[c];
             se += r * r;
             if (a.r_out) a.r_out[a.perm[j]] = r;
         }
