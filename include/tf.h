@@ -170,6 +170,13 @@ tf_status tf_predict(tf_ctx *ctx, int64_t m, const int32_t *d_idx, double *d_out
 /* Factor n as FP64 (host[I_n x K]); set marks the residual stale until
  * tf_resync.  Values are rounded to the storage precision. */
 tf_status tf_get_factor(tf_ctx *ctx, int32_t n, double *h);
+/* A block of factor n as FP64, host[nrows x ncols] row-major:
+ * h[r * ncols + c] = a^(n)_{h_rows[r], h_cols[c]}.  h_rows NULL means all rows
+ * in order (nrows must be I_n), h_cols NULL all columns (ncols must be K);
+ * entries may repeat.  Reads a few rows or columns of a wide factor without
+ * copying all of it.  TF_E_INVALID for a count or an index out of range. */
+tf_status tf_get_factor_block(tf_ctx *ctx, int32_t n, int64_t nrows, const int32_t *h_rows,
+                              int32_t ncols, const int32_t *h_cols, double *h);
 tf_status tf_set_factor(tf_ctx *ctx, int32_t n, const double *h);
 
 /* r = x - reconstruction recomputed from the current factors (definition

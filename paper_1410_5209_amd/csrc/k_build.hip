@@ -386,6 +386,34 @@ hipError_t gather_copy(int prec, const void *in, const int32_t *idx, int64_t nnz
     return hipGetLastError();
 }
 
+// A block of a factor as FP64: out[r * ncols + c] = A[row(r)][col(c)], where
+// row(r) = rows[r] (r when rows is NULL) and col(c) = cols[c] (c when NULL).
+template <int PREC>
+__global__ void k_factor_block(const void *A, int K, const int32_t *rows, int64_t nrows,
+                               const int32_t *cols, int ncols, double *out)
+{
+    using TS = typename Types<PREC>::TS;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nrows * ncols) return;
+    const int64_t r = t / ncols;
+    const int c = (int)(t - r * ncols);
+    const int64_t i = rows ? rows[r] : r;
+    const int k = cols ? cols[c] : c;
+    out[t] = load_f64(reinterpret_cast<const TS *>(A) + i * K + k);
+}
+
+hipError_t factor_block_to_f64(int prec, const void *A, int K, const int32_t *rows,
+                               int64_t nrows, const int32_t *cols, int ncols, double *out,
+                               hipStream_t st)
+{
+    const int64_t grid = (nrows * ncols + 255) / 256;
+    if (grid == 0) return hipSuccess;
+    if (prec == P_F64) hipLaunchKernelGGL(k_factor_block<P_F64>, dim3((unsigned)grid), dim3(256), 0, st, A, K, rows, nrows, cols, ncols, out);
+    else if (prec == P_F32) hipLaunchKernelGGL(k_factor_block<P_F32>, dim3((unsigned)grid), dim3(256), 0, st, A, K, rows, nrows, cols, ncols, out);
+    else hipLaunchKernelGGL(k_factor_block<P_BF16>, dim3((unsigned)grid), dim3(256), 0, st, A, K, rows, nrows, cols, ncols, out);
+    return hipGetLastError();
+}
+
 template <int PREC>
 __global__ void k_to_f64(const void *A, int64_t n, double *out)
 {

@@ -990,6 +990,45 @@ tf_status tf_get_factor(tf_ctx *ctx, int32_t n, double *h)
     return TF_OK;
 }
 
+tf_status tf_get_factor_block(tf_ctx *ctx, int32_t n, int64_t nrows, const int32_t *h_rows,
+                             int32_t ncols, const int32_t *h_cols, double *h)
+{
+    if (!ctx) return TF_E_INVALID;
+    if (n < 0 || n >= ctx->N || !h) return CTX_FAIL(ctx, TF_E_INVALID, "bad mode or NULL output");
+    const int64_t I = ctx->m[n].I;
+    if (h_rows ? (nrows < 1 || nrows > I) : nrows != I)
+        return CTX_FAIL(ctx, TF_E_INVALID, "row count %lld does not fit mode %d", (long long)nrows, n);
+    if (h_cols ? (ncols < 1 || ncols > ctx->K) : ncols != ctx->K)
+        return CTX_FAIL(ctx, TF_E_INVALID, "column count %d does not fit K = %d", ncols, ctx->K);
+    if (h_rows)
+        for (int64_t q = 0; q < nrows; ++q)
+            if (h_rows[q] < 0 || h_rows[q] >= I) return CTX_FAIL(ctx, TF_E_INVALID, "row %d out of range", h_rows[q]);
+    if (h_cols)
+        for (int q = 0; q < ncols; ++q)
+            if (h_cols[q] < 0 || h_cols[q] >= ctx->K) return CTX_FAIL(ctx, TF_E_INVALID, "column %d out of range", h_cols[q]);
+    const int64_t cnt = nrows * ncols;
+    double *d = nullptr;
+    int32_t *dr = nullptr, *dc = nullptr;
+    HIPCHK(ctx, dalloc(&d, (size_t)cnt));
+    hipError_t e = hipSuccess;
+    if (h_rows) {
+        e = hipMalloc(&dr, (size_t)nrows * sizeof(int32_t));
+        if (e == hipSuccess) e = hipMemcpy(dr, h_rows, (size_t)nrows * sizeof(int32_t), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess && h_cols) {
+        e = hipMalloc(&dc, (size_t)ncols * sizeof(int32_t));
+        if (e == hipSuccess) e = hipMemcpy(dc, h_cols, (size_t)ncols * sizeof(int32_t), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = factor_block_to_f64(ctx->prec, ctx->m[n].A, ctx->K, dr, nrows, dc, ncols, d, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess) e = hipMemcpy(h, d, (size_t)cnt * sizeof(double), hipMemcpyDeviceToHost);
+    dfree(d);
+    if (dr) (void)hipFree(dr);
+    if (dc) (void)hipFree(dc);
+    if (e != hipSuccess) return CTX_FAIL(ctx, TF_E_DEVICE, "get_factor_block: %s", hipGetErrorString(e));
+    return TF_OK;
+}
+
 tf_status tf_set_factor(tf_ctx *ctx, int32_t n, const double *h)
 {
     if (!ctx) return TF_E_INVALID;

@@ -135,6 +135,9 @@ hipError_t gather_copy(int prec, const void *in, const int32_t *idx, int64_t nnz
 hipError_t gather_residual(int prec, const double *r_in, const int32_t *perm, int64_t nnz,
                            void *rhat_out, hipStream_t st);
 hipError_t factor_to_f64(int prec, const void *A, int64_t n, double *out, hipStream_t st);
+hipError_t factor_block_to_f64(int prec, const void *A, int K, const int32_t *rows,
+                               int64_t nrows, const int32_t *cols, int ncols, double *out,
+                               hipStream_t st);
 hipError_t factor_from_f64(int prec, const double *in, int64_t n, void *A, hipStream_t st);
 
 // ---------------------------------------------------------------- slabs

@@ -69,6 +69,9 @@ class SparseCP:
     def factor(self, n):
         return tf.tf_get_factor(self.ctx, n, self.dims[n], self.K)
 
+    def factor_block(self, n, rows=None, cols=None):
+        return tf.tf_get_factor_block(self.ctx, n, self.dims[n], self.K, rows, cols)
+
     def factors(self):
         return [self.factor(n) for n in range(self.N)]
 

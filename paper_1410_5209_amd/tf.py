@@ -110,6 +110,7 @@ def lib():
         L.tf_loss.argtypes = [P, ctypes.POINTER(f64), ctypes.POINTER(f64)]
         L.tf_predict.argtypes = [P, i64, P, P]
         L.tf_get_factor.argtypes = [P, i32, P]
+        L.tf_get_factor_block.argtypes = [P, i32, ctypes.c_int64, P, i32, P, P]
         L.tf_set_factor.argtypes = [P, i32, P]
         L.tf_resync.argtypes = [P]
         L.tf_get_residual.argtypes = [P, P]
@@ -130,7 +131,8 @@ def lib():
         L.tf_serve_close.argtypes = [P]
         L.tf_serve_close.restype = None
         for name in ("tf_init", "tf_sweep", "tf_split", "tf_set_col_order", "tf_get_col_order",
-                     "tf_loss", "tf_predict", "tf_get_factor", "tf_set_factor", "tf_resync",
+                     "tf_loss", "tf_predict", "tf_get_factor", "tf_get_factor_block", "tf_set_factor",
+                     "tf_resync",
                      "tf_get_residual", "tf_get_csr", "tf_profile", "tf_profile_read",
                      "tf_plan_rows", "tf_foldin", "tf_serve_open", "tf_serve_submit",
                      "tf_serve_wait", "tf_serve_replay", "tf_serve_report",
@@ -213,6 +215,18 @@ def tf_loss(ctx):
 
 def tf_predict(ctx, d_idx, d_out):
     _check(ctx, lib().tf_predict(ctx, int(d_idx.shape[0]), _dev(d_idx), _dev(d_out)))
+
+
+def tf_get_factor_block(ctx, n, I, K, rows=None, cols=None):
+    """Rows `rows` and columns `cols` (None: all) of factor n as FP64."""
+    r = None if rows is None else np.ascontiguousarray(rows, dtype=np.int32)
+    c = None if cols is None else np.ascontiguousarray(cols, dtype=np.int32)
+    nr = int(I) if r is None else int(r.shape[0])
+    nc = int(K) if c is None else int(c.shape[0])
+    out = np.empty((nr, nc), dtype=np.float64)
+    _check(ctx, lib().tf_get_factor_block(ctx, int(n), nr, None if r is None else _np(r), nc,
+                                          None if c is None else _np(c), _np(out)))
+    return out
 
 
 def tf_get_factor(ctx, n, I, K):

@@ -1,0 +1,195 @@
+"""Checks at the full sizes of the benchmark workloads, in the configuration the
+benchmark times (tuned C and row tiles, a whole sweep), on properties that hold
+at any size, since the oracle cannot follow 1e8-entry tensors.
+
+* CSR (Table 1's row sets): the mode-n permutation is the stable sort of the
+  entry ids by row: rows nondecreasing along it, ids strictly increasing inside
+  a row, row counts and row pointers equal to the counts of the input indices.
+  Together these fix the permutation uniquely; checked bit-exact.
+* Split optimality (eq. (SALS)): after a split's last update of mode n each row
+  of mode n minimises the split's regularised least squares with the other
+  factors fixed, so its gradient vanishes:
+  sum_{j in Omega_i} r_j p_j = lambda a_i, with r the maintained residual and
+  p_j the elementwise product of the other modes' split columns at entry j.
+  Checked on sampled rows of the last mode, long rows (several workgroups per
+  row) among them, to 1e-4 of the summed magnitudes of the terms: FP32 storage
+  and accumulation leave ~1e-6, a wrong, missing or misplaced term leaves O(1),
+  a dropped lambda term O(1e-2) on the short rows.
+* Residual (R, Section 3.1): r_j = x_j - sum_k prod_n a^(n)_{i_n k} on sampled
+  entries, factors read back from the GPU and the sum taken in FP64 on the host,
+  to 1e-4 of |x_j| + sum_k prod_n |a^(n)_{i_n k}| (FP32 storage, K/C
+  incremental updates per sweep).  Predictions (tf_predict) on the same entries
+  to the same bound.
+* Loss (eq. (TF), 3-way): tf_loss equals sum r^2 + lambda sum_n ||A^(n)||_F^2
+  recomputed on the host from the read-back residual and factors, to 1e-10.
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import note
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def _check_csr(m, idx, n, I):
+    rp, pm = m.csr(n)
+    col = np.ascontiguousarray(idx[:, n])
+    counts = np.bincount(col, minlength=I)
+    assert rp.shape[0] == I + 1 and rp[0] == 0
+    assert np.array_equal(rp[1:], np.cumsum(counts)), f"mode {n}: row pointers"
+    assert pm.min() >= 0 and pm.max() < idx.shape[0], f"mode {n}: ids out of range"
+    rows = col[pm]
+    del col
+    assert np.all(rows[1:] >= rows[:-1]), f"mode {n}: rows not sorted along the permutation"
+    assert np.array_equal(np.bincount(rows, minlength=I), counts), f"mode {n}: row counts"
+    same = rows[1:] == rows[:-1]
+    del rows
+    assert np.all(np.diff(pm)[same] > 0), f"mode {n}: ids not increasing inside a row"
+    return rp, pm
+
+
+def _rows_to_check(rp, rng, n_random, n_long, long_range, cap_len):
+    lens = np.diff(rp)
+    nonempty = np.flatnonzero(lens > 0)
+    pick = [rng.choice(nonempty, size=min(n_random, nonempty.size), replace=False)]
+    lo, hi = long_range
+    longs = np.flatnonzero((lens >= max(lo, 1)) & (lens <= hi))
+    if n_long and longs.size:
+        pick.append(rng.choice(longs, size=min(n_long, longs.size), replace=False))
+    capped = np.flatnonzero(lens <= cap_len)
+    if capped.size:
+        pick.append(capped[np.argsort(lens[capped], kind="stable")[-3:]])  # the longest ones
+    return np.unique(np.concatenate(pick)).astype(np.int64)
+
+
+def _gather_products(m, idx, J, skip, cols):
+    """p_j over the modes other than `skip`, for entries J, columns cols."""
+    P = np.ones((J.shape[0], len(cols) if cols is not None else m.K))
+    for t in range(m.N):
+        if t == skip:
+            continue
+        u, inv = np.unique(idx[J, t], return_inverse=True)
+        P *= m.factor_block(t, u, cols)[inv]
+    return P
+
+
+def _check_split_optimality(m, idx, resid, rp, pm, rows, cols, lam, reg_mode, batch=300_000):
+    n = m.N - 1
+    lens = (rp[rows + 1] - rp[rows]).astype(np.int64)
+    assert np.all(lens > 0)
+    worst, checked = 0.0, 0
+    q = 0
+    while q < rows.shape[0]:
+        e = q
+        tot = 0
+        while e < rows.shape[0] and (e == q or tot + lens[e] <= batch):
+            tot += lens[e]
+            e += 1
+        br, bl = rows[q:e], lens[q:e]
+        J = np.concatenate([pm[rp[i]:rp[i + 1]] for i in br]).astype(np.int64)
+        seg = np.repeat(np.arange(br.shape[0]), bl)
+        starts = np.concatenate([[0], np.cumsum(bl)[:-1]])
+        P = _gather_products(m, idx, J, n, cols)
+        a = m.factor_block(n, br, cols)
+        r = resid[J]
+        g = np.add.reduceat(r[:, None] * P, starts, axis=0)
+        s = np.abs(r) + (np.abs(P) * np.abs(a[seg])).sum(axis=1)
+        lw = lam * (bl[:, None].astype(np.float64) if reg_mode == 1 else 1.0)
+        scale = np.add.reduceat(np.abs(P) * s[:, None], starts, axis=0) + lw * np.abs(a)
+        err = np.abs(g - lw * a) / np.maximum(scale, 1e-300)
+        worst = max(worst, float(err.max()))
+        checked += br.shape[0]
+        q = e
+    return worst, checked
+
+
+def _check_residual(m, idx, x, resid, rng, nsample):
+    J = np.unique(rng.integers(0, idx.shape[0], size=nsample))
+    P = _gather_products(m, idx, J, -1, None)
+    xh = P.sum(axis=1)
+    scale = np.abs(x[J]) + np.abs(P).sum(axis=1)
+    err_r = float(np.max(np.abs(resid[J] - (x[J] - xh)) / scale))
+    err_p = float(np.max(np.abs(m.predict(idx[J]) - xh) / scale))
+    return err_r, err_p
+
+
+def _model(w, idx, x, T_in, cands):
+    from paper_1410_5209_amd.model import SparseCP
+    m = SparseCP(w.dims, idx, x, w.K, w.lam, precision=w.prec)
+    r = m.autotune(T_in, cands, tune_tiles=True)
+    return m, int(r.best_C)
+
+
+@pytest.mark.timeout(900)
+def test_fullsize_3way():
+    """3-way 1M^3, 1e8 uniform entries, K = 100, FP32, C = 10, T_in = 2."""
+    w = synth.WORKLOADS["sals-3way-1m-fp32"]
+    note(f"fullsize {w.name}: generating {w.nnz} entries")
+    idx, x = synth.make_tensor(w)
+    note(f"fullsize {w.name}: init + autotune C in [{w.C}]")
+    m, C = _model(w, idx, x, w.T_in, [w.C])
+    assert C == w.C
+    for n in range(w.N):
+        note(f"fullsize {w.name}: CSR mode {n}")
+        rp, pm = _check_csr(m, idx, n, w.dims[n])
+    note(f"fullsize {w.name}: one sweep C={C} T_in={w.T_in}")
+    m.sweep(C, w.T_in)
+    loss, _ = m.loss()
+    resid = m.residual()
+    rng = np.random.default_rng(11)
+    last = m.col_order()[w.K - C:]
+    rows = _rows_to_check(rp, rng, 3000, 0, (0, 0), 10**9)
+    worst, nrows = _check_split_optimality(m, idx, resid, rp, pm, rows, last, w.lam, 0)
+    note(f"fullsize {w.name}: split optimality over {nrows} rows: {worst:.3g}")
+    assert worst <= TOL
+    er, ep = _check_residual(m, idx, x, resid, rng, 4000)
+    note(f"fullsize {w.name}: residual {er:.3g} predict {ep:.3g}")
+    assert er <= TOL and ep <= TOL
+    F = m.factors()
+    ref = float(np.dot(resid, resid)) + w.lam * sum(float(np.sum(A * A)) for A in F)
+    assert abs(loss - ref) <= 1e-10 * ref, (loss, ref)
+    m.close()
+
+
+@pytest.mark.timeout(900)
+def test_fullsize_5way_zipf():
+    """5-way 1M^5, 5e8 Zipf(1.0) draws, K = 1000, FP32; C tuned over {16, 32}, T_in = 1.
+
+    The sweep's last split is ragged (K mod C columns), so a further split of C
+    columns checks the tuned kernel too."""
+    w = synth.WORKLOADS["sals-5way-zipf-fp32"]
+    note(f"fullsize {w.name}: generating {w.nnz} draws")
+    idx, x = synth.make_tensor(w)
+    note(f"fullsize {w.name}: init + autotune C in [16, 32]")
+    m, C = _model(w, idx, x, w.T_in, [16, 32])
+    last_mode = w.N - 1
+    for n in (0, last_mode):
+        note(f"fullsize {w.name}: CSR mode {n}")
+        rp, pm = _check_csr(m, idx, n, w.dims[n])
+    rng = np.random.default_rng(12)
+    # short rows at random, 20 rows split across workgroups, the 3 longest
+    # rows of at most 2e5 entries (the longest rows hold ~3e7 entries)
+    rows = _rows_to_check(rp, rng, 2000, 20, (8192, 50_000), 200_000)
+    order = m.col_order()
+    note(f"fullsize {w.name}: one sweep C={C} T_in={w.T_in}")
+    m.sweep(C, w.T_in)
+    tail = w.K % C or C
+    resid = m.residual()
+    worst, nrows = _check_split_optimality(m, idx, resid, rp, pm, rows, order[w.K - tail:], w.lam, 0)
+    note(f"fullsize {w.name}: last split ({tail} columns) optimality over {nrows} rows: {worst:.3g}")
+    assert worst <= TOL
+    er, ep = _check_residual(m, idx, x, resid, rng, 3000)
+    note(f"fullsize {w.name}: residual {er:.3g} predict {ep:.3g}")
+    assert er <= TOL and ep <= TOL
+    cols = order[w.K // 2:w.K // 2 + C]
+    note(f"fullsize {w.name}: split of {C} columns")
+    m.split(cols, w.T_in)
+    del resid
+    resid = m.residual()
+    worst, nrows = _check_split_optimality(m, idx, resid, rp, pm, rows, cols, w.lam, 0)
+    note(f"fullsize {w.name}: {C}-column split optimality over {nrows} rows: {worst:.3g}")
+    assert worst <= TOL
+    m.close()
