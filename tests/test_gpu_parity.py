@@ -403,3 +403,48 @@ def test_autotune_leaves_model_unchanged_and_sweeps_with_chosen_width():
     ol, orr = o.loss()
     assert abs(gl - ol) <= 1e-4 * ol and abs(gr - orr) <= 1e-4 * orr
     g.close()
+
+
+@pytest.mark.parametrize("case", ["one_entry", "rank_one", "matrix_als"])
+def test_degenerate_sizes_f64(case):
+    """A tensor with a single entry (all other rows of every mode empty), rank
+    K = 1 (every split is the C = 1 update), and a 2-way matrix at C = K."""
+    if case == "one_entry":
+        dims, nnz, K, C, T_in = [5, 4, 3], 1, 3, 3, 1
+    elif case == "rank_one":
+        dims, nnz, K, C, T_in = [30, 20, 10], 500, 1, 1, 2
+    else:
+        dims, nnz, K, C, T_in = [70, 50], 2000, 6, 6, 1
+    note(f"degenerate {case} dims={dims} nnz={nnz} K={K}")
+    idx, x, A = problem(300, dims, nnz, K)
+    g, o = pair(dims, idx, x, A, K, 0.3, "f64")
+    for _ in range(2):
+        g.sweep(C, T_in)
+        o.sweep(C, T_in)
+        for n in range(len(dims)):
+            assert rel_max(g.factor(n), o.get_factor(n)) < 1e-10, n
+    gl, _ = g.loss()
+    ol, _ = o.loss()
+    assert abs(gl - ol) <= 1e-9 * ol
+    g.close()
+
+
+def test_factor_block_reads_chosen_rows_and_columns():
+    from paper_1410_5209_amd import tf
+    dims, K = [50, 40, 30], 12
+    note("factor block")
+    idx, x, A = problem(301, dims, 3000, K)
+    for prec in ("f64", "f32", "bf16"):
+        g, _ = pair(dims, idx, x, A, K, 0.3, prec)
+        g.split([0, 1, 2, 3], 1)
+        F = g.factor(1)
+        rows, cols = np.array([39, 0, 7, 7]), np.array([11, 2, 2])
+        assert np.array_equal(g.factor_block(1, rows, cols), F[rows][:, cols])
+        assert np.array_equal(g.factor_block(1, rows, None), F[rows])
+        assert np.array_equal(g.factor_block(1, None, cols), F[:, cols])
+        assert np.array_equal(g.factor_block(1), F)
+        for bad in (dict(rows=[40]), dict(cols=[12]), dict(rows=[-1]), dict(cols=[])):
+            with pytest.raises(tf.TFError) as e:
+                g.factor_block(1, bad.get("rows"), bad.get("cols"))
+            assert e.value.status == tf.TF_E_INVALID
+        g.close()
