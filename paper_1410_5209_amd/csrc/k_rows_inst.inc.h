@@ -52,10 +52,14 @@ static hipError_t reduce_cp(const int32_t *rows, const int32_t *ptr, int nsplit,
 template <int PREC, int NO>
 static hipError_t accum_wide_no(bool first, const AccumArgs &a, int grid, hipStream_t st)
 {
-    if (first)
-        hipLaunchKernelGGL((k_accum_wide<PREC, NO, true>), dim3(grid), dim3(256), 0, st, a);
+    bool any_before = false;
+    for (int l = 0; l < NO; ++l) any_before |= a.before[l] != 0;
+    if (first && any_before)
+        hipLaunchKernelGGL((k_accum_wide<PREC, NO, 2>), dim3(grid), dim3(256), 0, st, a);
+    else if (first)
+        hipLaunchKernelGGL((k_accum_wide<PREC, NO, 1>), dim3(grid), dim3(256), 0, st, a);
     else
-        hipLaunchKernelGGL((k_accum_wide<PREC, NO, false>), dim3(grid), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_accum_wide<PREC, NO, 0>), dim3(grid), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -66,7 +66,10 @@ __device__ __forceinline__ float half_sum(float v)
     return v;
 }
 
-template <int PREC, int NO, bool FIRST>
+// FM: 0 a plain pass, 1 a split's first pass with no other mode updated yet
+// in the split (no split-start segments to read: they equal W), 2 a first
+// pass that reads them for the modes already updated.
+template <int PREC, int NO, int FM>
 __global__ __launch_bounds__(256) void k_accum_wide(AccumArgs a)
 {
     using TS = typename Types<PREC>::TS;
@@ -74,6 +77,7 @@ __global__ __launch_bounds__(256) void k_accum_wide(AccumArgs a)
     static_assert(sizeof(typename Types<PREC>::TA) == 4, "wide kernel accumulates in FP32");
     constexpr int NEP = gram_stride(WCP);
     constexpr int GS = 4;                        // steps whose loads are issued together
+    constexpr bool FIRST = FM > 0;
 
     const int lane = threadIdx.x & 63;
     const int half = lane >> 5;
@@ -142,7 +146,7 @@ __global__ __launch_bounds__(256) void k_accum_wide(AccumArgs a)
                             w[q][l] = load_raw(reinterpret_cast<const TS *>(a.W[l]) + off, c);
                             if constexpr (FIRST) {
                                 if (a.has_pend) pv[q][l] = load_raw(reinterpret_cast<const TS *>(a.P[l]) + off, c);
-                                if (a.before[l]) sv[q][l] = load_raw(reinterpret_cast<const TS *>(a.S[l]) + off, c);
+                                if (FM == 2 && a.before[l]) sv[q][l] = load_raw(reinterpret_cast<const TS *>(a.S[l]) + off, c);
                             }
                         }
                     }
@@ -163,7 +167,7 @@ __global__ __launch_bounds__(256) void k_accum_wide(AccumArgs a)
 #pragma unroll
                         for (int l = 0; l < NO; ++l) {
                             tp *= col_value<TS>(pv[q][l], c);
-                            ts *= a.before[l] ? col_value<TS>(sv[q][l], c) : wv[l];
+                            ts *= (FM == 2 && a.before[l]) ? col_value<TS>(sv[q][l], c) : wv[l];
                         }
                         r = (r - half_sum(tp)) + half_sum(ts);
                         const float rh0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r), 0));
