@@ -55,6 +55,30 @@ typedef int32_t tf_status;
 #define TF_STRATEGY_SKEW 1   /* rows bucketed by length (1..64 lanes per row),
                                 rows above split_threshold cut into chunks whose
                                 partial Gram matrices are summed in a fixed order */
+#define TF_STRATEGY_AUTO 2   /* SKEW, with each mode's row tiles chosen by timed
+                                trial passes (as tf_autotune with the one
+                                candidate C, tune_tiles = 1) before the first
+                                split of each new compute width */
+
+/* Column order of tf_sweep (Algorithm 1 draws each split's columns without
+ * replacement; Section 5 keeps a fixed order for CDTF). */
+#define TF_ORDER_FIXED 0     /* the order set by tf_set_col_order (initially
+                                0..K-1): blocks of C consecutive entries */
+#define TF_ORDER_RANDOM 1    /* every tf_sweep first draws a permutation:
+                                sweep t (0, 1, ... counted per context) runs
+                                Fisher-Yates, for i = K-1 down to 1 swapping
+                                entries i and j = floor(u (i+1) / 2^53), where
+                                u is the top 53 bits of SplitMix64 output
+                                2^62 + t K + i for the context's seed (the
+                                generator the factor initialisation uses);
+                                tf_get_col_order returns it */
+
+/* Device memory hooks: alloc returns `bytes` of device memory on the
+ * context's device, aligned to 256 bytes, or NULL; free releases a block
+ * alloc returned (bytes is the size it was asked for).  stream is the
+ * context's stream.  Both may be called from a serving thread. */
+typedef void *(*tf_alloc_fn)(size_t bytes, void *stream, void *user);
+typedef void (*tf_free_fn)(void *ptr, size_t bytes, void *stream, void *user);
 
 typedef struct tf_options {
     uint32_t size;             /* sizeof(tf_options): versions the struct */
@@ -74,6 +98,14 @@ typedef struct tf_options {
                                   (0 = 2048) */
     int32_t resid_share;       /* TF_RESID_*: where the row passes of modes
                                   2..N read R-hat (default TF_RESID_AUTO) */
+    int32_t col_order;         /* TF_ORDER_* (default TF_ORDER_FIXED) */
+    size_t mem_budget;         /* device bytes the context may hold at once,
+                                  serving slots and call workspaces included;
+                                  an allocation beyond it fails with
+                                  TF_E_NOMEM (0 = no limit) */
+    tf_alloc_fn dev_alloc;     /* NULL (default): hipMalloc / hipFree; else */
+    tf_free_fn dev_free;       /*   every device allocation of the context */
+    void *alloc_user;          /*   goes through these two (both set) */
 } tf_options;
 
 /* Residual placement.  Mode 1 keeps R-hat in its own row order and forms it

@@ -67,6 +67,8 @@ def lib():
         L.or_splitmix64.argtypes = [u64, u64]
         L.or_splitmix64.restype = u64
         L.or_init_factors.argtypes = [P, u64, ctypes.c_int]
+        L.or_column_order.argtypes = [u64, i64, ctypes.c_int, P]
+        L.or_column_order.restype = None
         _lib = L
     return _lib
 
@@ -85,6 +87,13 @@ def get_threads() -> int:
 
 def splitmix64(seed: int, t: int) -> int:
     return int(lib().or_splitmix64(seed, t))
+
+
+def column_order(seed: int, t: int, K: int) -> np.ndarray:
+    """The random column order of sweep t (or_column_order)."""
+    out = np.empty(int(K), dtype=np.int32)
+    lib().or_column_order(int(seed), int(t), int(K), _p(out))
+    return out
 
 
 class OracleError(RuntimeError):

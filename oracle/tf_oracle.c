@@ -513,6 +513,26 @@ uint64_t or_splitmix64(uint64_t seed, uint64_t t)
     return z ^ (z >> 31);
 }
 
+/* Random column order of sweep t (Algorithm 1 picks each split's columns
+ * without replacement), the rule the library uses when asked for random
+ * orders: start from 0..K-1; walk i from K-1 down to 1; draw the SplitMix64
+ * output of counter 2^62 + t*K + i, keep its top 53 bits u, and swap
+ * positions i and floor(u * (i + 1) / 2^53), an index in [0, i]
+ * (Fisher and Yates' shuffle, in Durstenfeld's in-place form). */
+void or_column_order(uint64_t seed, int64_t t, int K, int32_t *out)
+{
+    for (int k = 0; k < K; ++k) out[k] = k;
+    for (int i = K - 1; i > 0; --i) {
+        uint64_t counter = ((uint64_t)1 << 62) + (uint64_t)t * (uint64_t)K + (uint64_t)i;
+        uint64_t u = or_splitmix64(seed, counter) >> 11;
+        unsigned __int128 prod = (unsigned __int128)u * (unsigned __int128)(uint64_t)(i + 1);
+        int j = (int)(uint64_t)(prod >> 53);
+        int32_t tmp = out[i];
+        out[i] = out[j];
+        out[j] = tmp;
+    }
+}
+
 void or_init_factors(or_ctx *c, uint64_t seed, int first_factor_zero)
 {
     uint64_t offset = 0;

@@ -307,7 +307,7 @@ void destroy_server(tf_server *s)
     for (auto &sl : s->slots) {
         if (sl->ev) (void)hipEventDestroy(sl->ev);
         if (sl->st) (void)hipStreamDestroy(sl->st);
-        if (sl->dev) (void)hipFree(sl->dev);
+        if (sl->dev) ctx_free(s->ctx, sl->dev);
         if (sl->hin) (void)hipHostFree(sl->hin);
         if (sl->hout) (void)hipHostFree(sl->hout);
         if (sl->hflags) (void)hipHostFree(sl->hflags);
@@ -364,7 +364,7 @@ tf_status tf_serve_open(tf_ctx *ctx, const tf_serve_opts *opts, tf_server **out)
         auto sl = std::make_unique<SSlot>();
         hipError_t e = hipStreamCreate(&sl->st);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl->ev, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipMalloc(&sl->dev, s->slot_bytes);
+        if (e == hipSuccess) e = ctx_alloc(ctx, &sl->dev, s->slot_bytes);
         if (e == hipSuccess) e = hipHostMalloc((void **)&sl->hin, s->slot_bytes, hipHostMallocDefault);
         if (e == hipSuccess)
             e = hipHostMalloc((void **)&sl->hout, (size_t)o.max_batch * ctx->K * 8, hipHostMallocDefault);
@@ -557,7 +557,7 @@ tf_status tf_foldin(tf_ctx *ctx, int32_t mode, int32_t nreq, const int64_t *h_re
                         align256((size_t)total * ctx->K * ta_bytes(ctx->prec)) +
                         align256((size_t)total * 8) + align256((size_t)nchunks * gs_bytes) + 256;
     void *ws = nullptr;
-    if (hipMalloc(&ws, need) != hipSuccess) return fail(TF_E_NOMEM, "fold-in workspace");
+    if (ctx_alloc(ctx, &ws, need) != hipSuccess) return fail(TF_E_NOMEM, "fold-in workspace");
     char *p = static_cast<char *>(ws);
     int64_t *d_ptr = reinterpret_cast<int64_t *>(p); p += align256((size_t)(nreq + 1) * 8);
     int32_t *d_tab = reinterpret_cast<int32_t *>(p); p += align256(h_tab.size() * 4);
@@ -603,7 +603,7 @@ tf_status tf_foldin(tf_ctx *ctx, int32_t mode, int32_t nreq, const int64_t *h_re
             st = TF_E_NUMERIC;
         }
     }
-    (void)hipFree(ws);
+    ctx_free(ctx, ws);
     if (e != hipSuccess) {
         ctx->err = std::string("fold-in: ") + hipGetErrorString(e);
         return TF_E_DEVICE;

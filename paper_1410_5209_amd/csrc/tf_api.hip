@@ -44,6 +44,54 @@ hipError_t launch_chunk_reduce(int prec, int CP, const int32_t *rows, const int3
 }
 }  // namespace tfk
 
+hipError_t ctx_alloc(tf_ctx *c, void **p, size_t bytes)
+{
+    *p = nullptr;
+    if (bytes == 0) bytes = 1;
+    {
+        std::lock_guard<std::mutex> g(c->mem_mu);
+        if (c->opt.mem_budget && c->mem_bytes + bytes > c->opt.mem_budget) return hipErrorOutOfMemory;
+        c->mem_bytes += bytes;  // reserved while the allocator runs
+    }
+    void *q = nullptr;
+    hipError_t e = hipSuccess;
+    if (c->opt.dev_alloc) {
+        q = c->opt.dev_alloc(bytes, c->opt.stream, c->opt.alloc_user);
+        if (!q) e = hipErrorOutOfMemory;
+        else if (reinterpret_cast<uintptr_t>(q) & 255) {
+            c->opt.dev_free(q, bytes, c->opt.stream, c->opt.alloc_user);
+            q = nullptr;
+            e = hipErrorInvalidValue;
+        }
+    } else {
+        e = hipMalloc(&q, bytes);
+    }
+    std::lock_guard<std::mutex> g(c->mem_mu);
+    if (e != hipSuccess) {
+        c->mem_bytes -= bytes;
+        return e;
+    }
+    c->mem_live[q] = bytes;
+    *p = q;
+    return hipSuccess;
+}
+
+void ctx_free(tf_ctx *c, void *p)
+{
+    if (!p) return;
+    size_t bytes = 0;
+    {
+        std::lock_guard<std::mutex> g(c->mem_mu);
+        auto it = c->mem_live.find(p);
+        if (it == c->mem_live.end()) return;  // not this context's block
+        bytes = it->second;
+        c->mem_live.erase(it);
+        c->mem_bytes -= bytes;
+    }
+    if (c->opt.dev_free) c->opt.dev_free(p, bytes, c->opt.stream, c->opt.alloc_user);
+    else (void)hipFree(p);
+}
+
 namespace {
 
 thread_local std::string g_init_err;
@@ -69,21 +117,20 @@ tf_status set_err(std::string *dst, tf_status s, const char *fmt, ...)
     do {                                                                                    \
         hipError_t e_ = (call);                                                             \
         if (e_ != hipSuccess)                                                               \
-            return CTX_FAIL(ctx, TF_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+            return CTX_FAIL(ctx, e_ == hipErrorOutOfMemory ? TF_E_NOMEM : TF_E_DEVICE,     \
+                            "%s failed: %s", #call, hipGetErrorString(e_));                \
     } while (0)
 
 template <typename T>
-hipError_t dalloc(T **p, size_t count)
+hipError_t dalloc(tf_ctx *c, T **p, size_t count)
 {
-    *p = nullptr;
-    if (count == 0) count = 1;
-    return hipMalloc((void **)p, count * sizeof(T));
+    void *q = nullptr;
+    const hipError_t e = ctx_alloc(c, &q, (count ? count : 1) * sizeof(T));
+    *p = static_cast<T *>(q);
+    return e;
 }
 
-void dfree(void *p)
-{
-    if (p) (void)hipFree(p);
-}
+void dfree(tf_ctx *c, void *p) { ctx_free(c, p); }
 
 int key_bits_for(int64_t I)
 {
@@ -102,12 +149,12 @@ tf_status ensure_gram(tf_ctx *c, int CP)
     }
     if (CP <= c->slab_cp && c->gram && maxch <= c->gpart_chunks) return TF_OK;
     const int cp = std::max(CP, c->slab_cp);
-    dfree(c->gram);
-    dfree(c->gpart);
+    dfree(c, c->gram);
+    dfree(c, c->gpart);
     c->gram = c->gpart = nullptr;
     const size_t rec = (size_t)gram_stride(cp) * ta_size(c->prec);
-    HIPCHK(c, hipMalloc(&c->gram, (size_t)maxI * rec));
-    HIPCHK(c, hipMalloc(&c->gpart, (size_t)maxch * rec));
+    HIPCHK(c, ctx_alloc(c, &c->gram, (size_t)maxI * rec));
+    HIPCHK(c, ctx_alloc(c, &c->gpart, (size_t)maxch * rec));
     c->slab_cp = cp;
     c->gpart_chunks = maxch;
     return TF_OK;
@@ -266,11 +313,11 @@ tf_status ensure_pos0(tf_ctx *c, int n)
     auto &md = c->m[n];
     if (md.pos0) return TF_OK;
     int32_t *inv = nullptr;
-    HIPCHK(c, hipMalloc(&md.pos0, (size_t)c->nnz * sizeof(int32_t)));
-    HIPCHK(c, hipMalloc(&inv, (size_t)c->nnz * sizeof(int32_t)));
+    HIPCHK(c, dalloc(c, &md.pos0, (size_t)c->nnz));
+    HIPCHK(c, dalloc(c, &inv, (size_t)c->nnz));
     hipError_t e = compose_with_mode0(c->m[0].perm, md.perm, c->nnz, inv, md.pos0, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    (void)hipFree(inv);
+    dfree(c, inv);
     if (e != hipSuccess) return CTX_FAIL(c, TF_E_DEVICE, "pos0: %s", hipGetErrorString(e));
     return TF_OK;
 }
@@ -397,9 +444,9 @@ tf_status check_ready(tf_ctx *c)
 tf_status ensure_partials(tf_ctx *c, int64_t n)
 {
     if (n <= c->partials_cap) return TF_OK;
-    dfree(c->d_partials);
+    dfree(c, c->d_partials);
     c->d_partials = nullptr;
-    HIPCHK(c, dalloc(&c->d_partials, (size_t)n));
+    HIPCHK(c, dalloc(c, &c->d_partials, (size_t)n));
     c->partials_cap = n;
     return TF_OK;
 }
@@ -450,19 +497,19 @@ void destroy_ctx(tf_ctx *c)
 {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    dfree(c->idx);
-    dfree(c->x);
+    dfree(c, c->idx);
+    dfree(c, c->x);
     for (int n = 0; n < kMaxModes; ++n) {
         auto &md = c->m[n];
-        dfree(md.rowptr); dfree(md.perm);
-        for (int l = 0; l < kMaxModes - 1; ++l) dfree(md.oidx[l]);
-        dfree(md.rhat); dfree(md.A); dfree(md.Z);
-        dfree(md.tasks); dfree(md.items); dfree(md.chunks);
-        dfree(md.split_rows); dfree(md.split_chunk_ptr);
-        dfree(md.pos0);
+        dfree(c, md.rowptr); dfree(c, md.perm);
+        for (int l = 0; l < kMaxModes - 1; ++l) dfree(c, md.oidx[l]);
+        dfree(c, md.rhat); dfree(c, md.A); dfree(c, md.Z);
+        dfree(c, md.tasks); dfree(c, md.items); dfree(c, md.chunks);
+        dfree(c, md.split_rows); dfree(c, md.split_chunk_ptr);
+        dfree(c, md.pos0);
     }
-    dfree(c->gram); dfree(c->gpart); dfree(c->d_cols); dfree(c->d_bad);
-    dfree(c->d_partials); dfree(c->d_scalar);
+    dfree(c, c->gram); dfree(c, c->gpart); dfree(c, c->d_cols); dfree(c, c->d_bad);
+    dfree(c, c->d_partials); dfree(c, c->d_scalar);
     for (auto e : c->ev_free) (void)hipEventDestroy(e);
     for (auto &t : c->ev_pending) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
     delete c;
@@ -471,7 +518,7 @@ void destroy_ctx(tf_ctx *c)
 template <typename T>
 tf_status upload_vec(tf_ctx *c, T **dst, const std::vector<T> &v)
 {
-    HIPCHK(c, dalloc(dst, v.size()));
+    HIPCHK(c, dalloc(c, dst, v.size()));
     if (!v.empty())
         HIPCHK(c, hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -483,9 +530,10 @@ tf_status apply_plan(tf_ctx *c, int n, int lane_nnz, int split_threshold, int ch
 {
     auto &md = c->m[n];
     HostPlan plan;
-    plan_rows(md.h_rowptr.data(), md.I, c->opt.strategy, lane_nnz, split_threshold, chunk_nnz, &plan);
+    const int strategy = c->opt.strategy == TF_STRATEGY_PLAIN ? TF_STRATEGY_PLAIN : TF_STRATEGY_SKEW;
+    plan_rows(md.h_rowptr.data(), md.I, strategy, lane_nnz, split_threshold, chunk_nnz, &plan);
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    dfree(md.tasks); dfree(md.items); dfree(md.chunks); dfree(md.split_rows); dfree(md.split_chunk_ptr);
+    dfree(c, md.tasks); dfree(c, md.items); dfree(c, md.chunks); dfree(c, md.split_rows); dfree(c, md.split_chunk_ptr);
     md.tasks = nullptr; md.items = nullptr; md.chunks = nullptr;
     md.split_rows = nullptr; md.split_chunk_ptr = nullptr;
     tf_status s;
@@ -508,13 +556,13 @@ tf_status build_state(tf_ctx *c, const int32_t *d_idx, const double *d_vals)
     const int N = c->N;
     const int64_t nnz = c->nnz;
     hipStream_t st = c->stream;
-    HIPCHK(c, dalloc(&c->idx, (size_t)nnz * N));
-    HIPCHK(c, dalloc(&c->x, (size_t)nnz));
+    HIPCHK(c, dalloc(c, &c->idx, (size_t)nnz * N));
+    HIPCHK(c, dalloc(c, &c->x, (size_t)nnz));
     HIPCHK(c, hipMemcpyAsync(c->idx, d_idx, (size_t)nnz * N * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
     HIPCHK(c, hipMemcpyAsync(c->x, d_vals, (size_t)nnz * sizeof(double), hipMemcpyDeviceToDevice, st));
-    HIPCHK(c, dalloc(&c->d_bad, kMaxModes));
-    HIPCHK(c, dalloc(&c->d_scalar, 4));
-    HIPCHK(c, dalloc(&c->d_cols, 2 * (size_t)c->K + 2));
+    HIPCHK(c, dalloc(c, &c->d_bad, kMaxModes));
+    HIPCHK(c, dalloc(c, &c->d_scalar, 4));
+    HIPCHK(c, dalloc(c, &c->d_cols, 2 * (size_t)c->K + 2));
 
     // validation: first bad index tuple and first non-finite value
     HIPCHK(c, hipMemsetAsync(c->d_bad, 0xff, 2 * sizeof(unsigned long long), st));
@@ -531,27 +579,27 @@ tf_status build_state(tf_ctx *c, const int32_t *d_idx, const double *d_vals)
     int32_t *k0 = nullptr, *k1 = nullptr, *v1 = nullptr, *hist = nullptr, *stmp = nullptr;
     const int64_t hcap = sort_hist_size(nnz);
     const int64_t scap = scan_tmp_size(hcap);
-    struct Tmp { int32_t **p; ~Tmp() { for (int i = 0; i < 5; ++i) dfree(p[i]); } };
+    struct Tmp { tf_ctx *c; int32_t **p; ~Tmp() { for (int i = 0; i < 5; ++i) dfree(c, p[i]); } };
     int32_t *tmps[5] = {nullptr};
-    Tmp guard{tmps};
-    HIPCHK(c, dalloc(&k0, (size_t)nnz)); tmps[0] = k0;
-    HIPCHK(c, dalloc(&k1, (size_t)nnz)); tmps[1] = k1;
-    HIPCHK(c, dalloc(&v1, (size_t)nnz)); tmps[2] = v1;
-    HIPCHK(c, dalloc(&hist, (size_t)hcap)); tmps[3] = hist;
-    HIPCHK(c, dalloc(&stmp, (size_t)scap)); tmps[4] = stmp;
+    Tmp guard{c, tmps};
+    HIPCHK(c, dalloc(c, &k0, (size_t)nnz)); tmps[0] = k0;
+    HIPCHK(c, dalloc(c, &k1, (size_t)nnz)); tmps[1] = k1;
+    HIPCHK(c, dalloc(c, &v1, (size_t)nnz)); tmps[2] = v1;
+    HIPCHK(c, dalloc(c, &hist, (size_t)hcap)); tmps[3] = hist;
+    HIPCHK(c, dalloc(c, &stmp, (size_t)scap)); tmps[4] = stmp;
 
     for (int n = 0; n < N; ++n) {
         auto &md = c->m[n];
         md.I = c->dims[n];
-        HIPCHK(c, dalloc(&md.perm, (size_t)nnz));
-        HIPCHK(c, dalloc(&md.rowptr, (size_t)md.I + 1));
+        HIPCHK(c, dalloc(c, &md.perm, (size_t)nnz));
+        HIPCHK(c, dalloc(c, &md.rowptr, (size_t)md.I + 1));
         HIPCHK(c, stable_sort_by_key(c->idx, N, n, nnz, key_bits_for(md.I), md.perm, k0, k1, v1,
                                      hist, hcap, stmp, scap, st));
         HIPCHK(c, rowptr_from_sorted(k0, nnz, md.I, md.rowptr, st));
         int t = 0;
         for (int l = 0; l < N; ++l) {
             if (l == n) continue;
-            HIPCHK(c, dalloc(&md.oidx[t], (size_t)nnz));
+            HIPCHK(c, dalloc(c, &md.oidx[t], (size_t)nnz));
             HIPCHK(c, gather_other_index(c->idx, N, l, md.perm, nnz, md.oidx[t], st));
             ++t;
         }
@@ -569,18 +617,18 @@ tf_status build_state(tf_ctx *c, const int32_t *d_idx, const double *d_vals)
     uint64_t offset = 0;
     for (int n = 0; n < N; ++n) {
         auto &md = c->m[n];
-        HIPCHK(c, hipMalloc(&md.A, (size_t)md.I * c->K * sf));
+        HIPCHK(c, ctx_alloc(c, &md.A, (size_t)md.I * c->K * sf));
         const bool zero = c->opt.first_factor_zero && n == 0;
         HIPCHK(c, init_factor(c->prec, md.A, md.I, c->K, c->opt.seed, offset, zero, st));
         offset += (uint64_t)md.I * (uint64_t)c->K;
         const size_t slab = (size_t)md.I * kSlabRowBytes;
-        HIPCHK(c, hipMalloc(&md.Z, slab));
+        HIPCHK(c, ctx_alloc(c, &md.Z, slab));
         HIPCHK(c, hipMemsetAsync(md.Z, 0, slab, st));
-        HIPCHK(c, hipMalloc(&md.rhat, (size_t)nnz * tr_size(c->prec)));
+        HIPCHK(c, ctx_alloc(c, &md.rhat, (size_t)nnz * tr_size(c->prec)));
     }
     // residual r = x - reconstruction (exactly x when A^(1) = 0)
     double *r = nullptr;
-    HIPCHK(c, dalloc(&r, (size_t)nnz));
+    HIPCHK(c, dalloc(c, &r, (size_t)nnz));
     const void *A[kMaxModes];
     for (int n = 0; n < N; ++n) A[n] = c->m[n].A;
     hipError_t e = residual_input_order(c->prec, c->idx, c->x, nnz, N, A, c->K,
@@ -588,7 +636,7 @@ tf_status build_state(tf_ctx *c, const int32_t *d_idx, const double *d_vals)
     for (int n = 0; n < N && e == hipSuccess; ++n)
         e = gather_residual(c->prec, r, c->m[n].perm, nnz, c->m[n].rhat, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    dfree(r);
+    dfree(c, r);
     if (e != hipSuccess) return CTX_FAIL(c, TF_E_DEVICE, "residual: %s", hipGetErrorString(e));
     c->order.resize(c->K);
     for (int k = 0; k < c->K; ++k) c->order[k] = k;
@@ -615,6 +663,11 @@ void tf_default_options(tf_options *opt)
     opt->split_threshold = 4096;
     opt->chunk_nnz = 2048;
     opt->resid_share = TF_RESID_AUTO;
+    opt->col_order = TF_ORDER_FIXED;
+    opt->mem_budget = 0;
+    opt->dev_alloc = nullptr;
+    opt->dev_free = nullptr;
+    opt->alloc_user = nullptr;
 }
 
 const char *tf_last_error(const tf_ctx *ctx)
@@ -647,8 +700,12 @@ tf_status tf_init(tf_ctx **out, int32_t N, const int64_t *dims, int64_t nnz, con
     }
     if (o.precision < 0 || o.precision > 2) return set_err(&g_init_err, TF_E_INVALID, "bad precision");
     if (o.reg_mode != 0 && o.reg_mode != 1) return set_err(&g_init_err, TF_E_INVALID, "bad reg_mode");
-    if (o.strategy != TF_STRATEGY_PLAIN && o.strategy != TF_STRATEGY_SKEW)
+    if (o.strategy != TF_STRATEGY_PLAIN && o.strategy != TF_STRATEGY_SKEW && o.strategy != TF_STRATEGY_AUTO)
         return set_err(&g_init_err, TF_E_INVALID, "bad strategy");
+    if (o.col_order != TF_ORDER_FIXED && o.col_order != TF_ORDER_RANDOM)
+        return set_err(&g_init_err, TF_E_INVALID, "bad col_order");
+    if ((o.dev_alloc == nullptr) != (o.dev_free == nullptr))
+        return set_err(&g_init_err, TF_E_INVALID, "dev_alloc and dev_free must be set together");
     if (o.lane_nnz < 0 || o.split_threshold < 0 || o.chunk_nnz < 0)
         return set_err(&g_init_err, TF_E_INVALID, "negative tuning option");
     if (o.resid_share < TF_RESID_AUTO || o.resid_share > TF_RESID_SHARED)
@@ -684,6 +741,51 @@ tf_status tf_init(tf_ctx **out, int32_t N, const int64_t *dims, int64_t nnz, con
 
 void tf_destroy(tf_ctx *ctx) { destroy_ctx(ctx); }
 
+namespace {
+
+// SplitMix64 as a counter-based generator (the factor initialisation's):
+// output t for seed s is mix(s + t * 0x9E3779B97F4A7C15).
+uint64_t host_splitmix64(uint64_t seed, uint64_t t)
+{
+    uint64_t z = seed + t * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// The column permutation of sweep t under TF_ORDER_RANDOM: Fisher-Yates from
+// the last position down, position i swapped with j = floor(u (i+1) / 2^53),
+// u the top 53 bits of output 2^62 + t K + i.
+void draw_col_order(uint64_t seed, int64_t t, int K, std::vector<int32_t> &order)
+{
+    order.resize(K);
+    for (int k = 0; k < K; ++k) order[k] = k;
+    for (int i = K - 1; i >= 1; --i) {
+        const uint64_t ctr = (1ull << 62) + (uint64_t)t * (uint64_t)K + (uint64_t)i;
+        const uint64_t u = host_splitmix64(seed, ctr) >> 11;
+        const int j = (int)(((unsigned __int128)u * (unsigned)(i + 1)) >> 53);
+        std::swap(order[i], order[j]);
+    }
+}
+
+// TF_STRATEGY_AUTO: tune each mode's row tiles for the compute width of C
+// the first time a split of that width runs.
+tf_status auto_tiles(tf_ctx *c, int C, int T_in)
+{
+    if (c->opt.strategy != TF_STRATEGY_AUTO) return TF_OK;
+    const int cp = pick_cp(C, c->prec);
+    if (cp < 0 || cp == c->auto_cp) return TF_OK;
+    tf_tune_result r;
+    const int32_t cand = C;
+    const int keep = c->tuned_C;
+    tf_status s = tf_autotune(c, T_in, &cand, 1, 1, &r);
+    c->tuned_C = keep;
+    if (s == TF_OK) c->auto_cp = cp;
+    return s;
+}
+
+}  // namespace
+
 tf_status tf_split(tf_ctx *ctx, int32_t ncols, const int32_t *h_cols, int32_t T_in)
 {
     if (!ctx) return TF_E_INVALID;
@@ -697,6 +799,7 @@ tf_status tf_split(tf_ctx *ctx, int32_t ncols, const int32_t *h_cols, int32_t T_
     if (ncols > kMaxC) return CTX_FAIL(ctx, TF_E_UNSUPPORTED, "C = %d exceeds %d", ncols, kMaxC);
     tf_status s = check_ready(ctx);
     if (s != TF_OK) return s;
+    if ((s = auto_tiles(ctx, ncols, T_in)) != TF_OK) return s;
     if ((s = reset_bad(ctx)) != TF_OK) return s;
     if ((s = run_split(ctx, h_cols, ncols, T_in)) != TF_OK) return s;
     return check_bad(ctx);
@@ -713,7 +816,10 @@ tf_status tf_sweep(tf_ctx *ctx, int32_t C, int32_t T_in)
     if (C > kMaxC) return CTX_FAIL(ctx, TF_E_UNSUPPORTED, "C = %d exceeds %d", C, kMaxC);
     tf_status s = check_ready(ctx);
     if (s != TF_OK) return s;
+    if ((s = auto_tiles(ctx, C, T_in)) != TF_OK) return s;
     if ((s = reset_bad(ctx)) != TF_OK) return s;
+    if (ctx->opt.col_order == TF_ORDER_RANDOM) draw_col_order(ctx->opt.seed, ctx->sweeps_run, ctx->K, ctx->order);
+    ctx->sweeps_run += 1;
     for (int b = 0; b < ctx->K; b += C) {
         const int w = std::min(C, ctx->K - b);
         if ((s = run_split(ctx, ctx->order.data() + b, w, T_in)) != TF_OK) return s;
@@ -820,8 +926,8 @@ extern "C" tf_status tf_autotune(tf_ctx *ctx, int32_t T_in, const int32_t *h_can
     const auto t_start = std::chrono::steady_clock::now();
     std::memset(out, 0, sizeof *out);
     void *scratch = nullptr;
-    HIPCHK(ctx, hipMalloc(&scratch, (size_t)ctx->nnz * tr_size(ctx->prec)));
-    struct Free { void *p; ~Free() { dfree(p); } } guard{scratch};
+    HIPCHK(ctx, ctx_alloc(ctx, &scratch, (size_t)ctx->nnz * tr_size(ctx->prec)));
+    struct Free { tf_ctx *c; void *p; ~Free() { dfree(c, p); } } guard{ctx, scratch};
     if ((s = reset_bad(ctx)) != TF_OK) return s;
 
     double best = 1e300;
@@ -944,14 +1050,14 @@ tf_status tf_get_residual(tf_ctx *ctx, double *h)
     tf_status s = check_ready(ctx);
     if (s != TF_OK) return s;
     double *d = nullptr;
-    HIPCHK(ctx, dalloc(&d, (size_t)ctx->nnz));
+    HIPCHK(ctx, dalloc(ctx, &d, (size_t)ctx->nnz));
     double se = 0.0;
     s = eval_residual(ctx, d, &se);
     if (s == TF_OK) {
         hipError_t e = hipMemcpy(h, d, (size_t)ctx->nnz * sizeof(double), hipMemcpyDeviceToHost);
         if (e != hipSuccess) s = CTX_FAIL(ctx, TF_E_DEVICE, "copy: %s", hipGetErrorString(e));
     }
-    dfree(d);
+    dfree(ctx, d);
     return s;
 }
 
@@ -959,7 +1065,7 @@ tf_status tf_resync(tf_ctx *ctx)
 {
     if (!ctx) return TF_E_INVALID;
     double *r = nullptr;
-    HIPCHK(ctx, dalloc(&r, (size_t)ctx->nnz));
+    HIPCHK(ctx, dalloc(ctx, &r, (size_t)ctx->nnz));
     const void *A[kMaxModes];
     for (int n = 0; n < ctx->N; ++n) A[n] = ctx->m[n].A;
     hipError_t e = residual_input_order(ctx->prec, ctx->idx, ctx->x, ctx->nnz, ctx->N, A, ctx->K,
@@ -967,7 +1073,7 @@ tf_status tf_resync(tf_ctx *ctx)
     for (int n = 0; n < ctx->N && e == hipSuccess; ++n)
         e = gather_residual(ctx->prec, r, ctx->m[n].perm, ctx->nnz, ctx->m[n].rhat, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-    dfree(r);
+    dfree(ctx, r);
     if (e != hipSuccess) return CTX_FAIL(ctx, TF_E_DEVICE, "resync: %s", hipGetErrorString(e));
     for (int n = 0; n < ctx->N; ++n) ctx->m[n].fresh = true;
     ctx->pend.clear();
@@ -981,11 +1087,11 @@ tf_status tf_get_factor(tf_ctx *ctx, int32_t n, double *h)
     if (n < 0 || n >= ctx->N || !h) return CTX_FAIL(ctx, TF_E_INVALID, "bad mode or NULL output");
     const int64_t cnt = ctx->m[n].I * ctx->K;
     double *d = nullptr;
-    HIPCHK(ctx, dalloc(&d, (size_t)cnt));
+    HIPCHK(ctx, dalloc(ctx, &d, (size_t)cnt));
     hipError_t e = factor_to_f64(ctx->prec, ctx->m[n].A, cnt, d, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e == hipSuccess) e = hipMemcpy(h, d, (size_t)cnt * sizeof(double), hipMemcpyDeviceToHost);
-    dfree(d);
+    dfree(ctx, d);
     if (e != hipSuccess) return CTX_FAIL(ctx, TF_E_DEVICE, "get_factor: %s", hipGetErrorString(e));
     return TF_OK;
 }
@@ -1009,22 +1115,22 @@ tf_status tf_get_factor_block(tf_ctx *ctx, int32_t n, int64_t nrows, const int32
     const int64_t cnt = nrows * ncols;
     double *d = nullptr;
     int32_t *dr = nullptr, *dc = nullptr;
-    HIPCHK(ctx, dalloc(&d, (size_t)cnt));
+    HIPCHK(ctx, dalloc(ctx, &d, (size_t)cnt));
     hipError_t e = hipSuccess;
     if (h_rows) {
-        e = hipMalloc(&dr, (size_t)nrows * sizeof(int32_t));
+        e = dalloc(ctx, &dr, (size_t)nrows);
         if (e == hipSuccess) e = hipMemcpy(dr, h_rows, (size_t)nrows * sizeof(int32_t), hipMemcpyHostToDevice);
     }
     if (e == hipSuccess && h_cols) {
-        e = hipMalloc(&dc, (size_t)ncols * sizeof(int32_t));
+        e = dalloc(ctx, &dc, (size_t)ncols);
         if (e == hipSuccess) e = hipMemcpy(dc, h_cols, (size_t)ncols * sizeof(int32_t), hipMemcpyHostToDevice);
     }
     if (e == hipSuccess) e = factor_block_to_f64(ctx->prec, ctx->m[n].A, ctx->K, dr, nrows, dc, ncols, d, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e == hipSuccess) e = hipMemcpy(h, d, (size_t)cnt * sizeof(double), hipMemcpyDeviceToHost);
-    dfree(d);
-    if (dr) (void)hipFree(dr);
-    if (dc) (void)hipFree(dc);
+    dfree(ctx, d);
+    dfree(ctx, dr);
+    dfree(ctx, dc);
     if (e != hipSuccess) return CTX_FAIL(ctx, TF_E_DEVICE, "get_factor_block: %s", hipGetErrorString(e));
     return TF_OK;
 }
@@ -1037,11 +1143,11 @@ tf_status tf_set_factor(tf_ctx *ctx, int32_t n, const double *h)
     for (int64_t t = 0; t < cnt; ++t)
         if (!std::isfinite(h[t])) return CTX_FAIL(ctx, TF_E_INVALID, "factor entry %lld is not finite", (long long)t);
     double *d = nullptr;
-    HIPCHK(ctx, dalloc(&d, (size_t)cnt));
+    HIPCHK(ctx, dalloc(ctx, &d, (size_t)cnt));
     hipError_t e = hipMemcpy(d, h, (size_t)cnt * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = factor_from_f64(ctx->prec, d, cnt, ctx->m[n].A, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-    dfree(d);
+    dfree(ctx, d);
     if (e != hipSuccess) return CTX_FAIL(ctx, TF_E_DEVICE, "set_factor: %s", hipGetErrorString(e));
     ctx->stale = true;
     return TF_OK;

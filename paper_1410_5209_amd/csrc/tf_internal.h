@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/tf.h"
@@ -238,6 +240,19 @@ struct tf_ctx {
     struct Timed { hipEvent_t a, b; double bytes; bool first; };
     std::vector<Timed> ev_pending;
     tf_kstats kstats{};
+    int64_t sweeps_run = 0;         // tf_sweep calls (keys the random column orders)
+    int auto_cp = 0;                // TF_STRATEGY_AUTO: width the tiles were tuned for
+
+    // device memory of the context (ctx_alloc / ctx_free): the caller's hooks
+    // or hipMalloc, counted against opt.mem_budget
+    std::mutex mem_mu;
+    std::unordered_map<void *, size_t> mem_live;
+    size_t mem_bytes = 0;
 
     std::string err;
 };
+
+// Device allocation for a context (see tf_options.mem_budget / dev_alloc):
+// hipErrorOutOfMemory when the budget or the allocator refuses.
+hipError_t ctx_alloc(tf_ctx *c, void **p, size_t bytes);
+void ctx_free(tf_ctx *c, void *p);

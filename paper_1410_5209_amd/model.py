@@ -12,10 +12,12 @@ class SparseCP:
 
     def __init__(self, dims, idx, vals, K, lam, precision="f32", reg_mode=0,
                  first_factor_zero=True, strategy=tf.TF_STRATEGY_SKEW, seed=2, stream=None,
-                 lane_nnz=2, split_threshold=4096, chunk_nnz=2048, resid_share=tf.TF_RESID_AUTO):
+                 lane_nnz=2, split_threshold=4096, chunk_nnz=2048, resid_share=tf.TF_RESID_AUTO,
+                 col_order=tf.TF_ORDER_FIXED, mem_budget=0, torch_alloc=False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("SparseCP needs a HIP GPU")
+        self._hooks = None
         self.dims = [int(d) for d in dims]
         self.N = len(self.dims)
         self.K = int(K)
@@ -32,7 +34,23 @@ class SparseCP:
                                     first_factor_zero=1 if first_factor_zero else 0,
                                     strategy=int(strategy), seed=int(seed), stream=stream,
                                     lane_nnz=int(lane_nnz), split_threshold=int(split_threshold),
-                                    chunk_nnz=int(chunk_nnz), resid_share=int(resid_share))
+                                    chunk_nnz=int(chunk_nnz), resid_share=int(resid_share),
+                                    col_order=int(col_order), mem_budget=int(mem_budget))
+        if torch_alloc:
+            # the library's device memory comes from torch's caching allocator
+            dev_index = torch.cuda.current_device()
+
+            def _alloc(nbytes, stream, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev_index, stream or None)
+                except Exception:  # out of memory: the library reports TF_E_NOMEM
+                    return None
+
+            def _free(ptr, nbytes, stream, user):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            self._hooks = (tf.ALLOC_FN(_alloc), tf.FREE_FN(_free))
+            opt.dev_alloc, opt.dev_free = self._hooks
         self.ctx = tf.tf_init(self.dims, d_idx, d_vals, self.K, self.lam, opt)
         del d_idx, d_vals  # the library keeps its own copies
 

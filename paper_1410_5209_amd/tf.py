@@ -17,8 +17,13 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "tf.h")
 
 TF_OK, TF_E_INVALID, TF_E_NOMEM, TF_E_DEVICE, TF_E_NUMERIC, TF_E_UNSUPPORTED, TF_E_BUSY, TF_E_STATE = range(8)
 TF_PREC_F64, TF_PREC_F32, TF_PREC_BF16 = 0, 1, 2
-TF_STRATEGY_PLAIN, TF_STRATEGY_SKEW = 0, 1
+TF_STRATEGY_PLAIN, TF_STRATEGY_SKEW, TF_STRATEGY_AUTO = 0, 1, 2
 TF_RESID_AUTO, TF_RESID_OWN, TF_RESID_SHARED = 0, 1, 2
+TF_ORDER_FIXED, TF_ORDER_RANDOM = 0, 1
+
+# device memory hooks (tf_alloc_fn / tf_free_fn)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 PREC = {"f64": TF_PREC_F64, "f32": TF_PREC_F32, "bf16": TF_PREC_BF16}
 
 
@@ -28,7 +33,9 @@ class tf_options(ctypes.Structure):
                 ("strategy", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("stream", ctypes.c_void_p), ("lane_nnz", ctypes.c_int32),
                 ("split_threshold", ctypes.c_int32), ("chunk_nnz", ctypes.c_int32),
-                ("resid_share", ctypes.c_int32)]
+                ("resid_share", ctypes.c_int32), ("col_order", ctypes.c_int32),
+                ("mem_budget", ctypes.c_size_t), ("dev_alloc", ALLOC_FN),
+                ("dev_free", FREE_FN), ("alloc_user", ctypes.c_void_p)]
 
 
 class tf_kstats(ctypes.Structure):

@@ -19,10 +19,12 @@ def test_library_exports_every_declared_symbol():
 
 def test_options_struct_matches_header_defaults():
     o = tf.tf_default_options()
-    assert o.size == ctypes.sizeof(tf.tf_options) == 56
+    assert o.size == ctypes.sizeof(tf.tf_options) == 96
     assert (o.precision, o.reg_mode, o.first_factor_zero, o.strategy, o.seed) == (1, 0, 1, 1, 2)
     assert (o.lane_nnz, o.split_threshold, o.chunk_nnz) == (2, 4096, 2048)
     assert o.resid_share == tf.TF_RESID_AUTO
+    assert o.col_order == tf.TF_ORDER_FIXED and o.mem_budget == 0
+    assert not o.dev_alloc and not o.dev_free and o.alloc_user is None
 
 
 def _rowptr(counts):
@@ -74,7 +76,12 @@ def test_init_rejects_bad_arguments_on_host():
         assert st == tf.TF_E_INVALID, (N, nnz, K, lam)
         assert ctx.value is None
         assert len(tf.tf_last_error(None)) > 0
-    o = tf.tf_default_options(precision=7)
-    st = L.tf_init(ctypes.byref(ctx), 3, dims.ctypes.data_as(ctypes.c_void_p), 10, fake, fake, 2,
-                   1.0, ctypes.byref(o))
-    assert st == tf.TF_E_INVALID
+    bad_opts = [tf.tf_default_options(precision=7), tf.tf_default_options(strategy=3),
+                tf.tf_default_options(col_order=2), tf.tf_default_options(resid_share=5)]
+    half = tf.tf_default_options()
+    half.dev_alloc = tf.ALLOC_FN(lambda n, s, u: None)   # dev_free left NULL
+    bad_opts.append(half)
+    for o in bad_opts:
+        st = L.tf_init(ctypes.byref(ctx), 3, dims.ctypes.data_as(ctypes.c_void_p), 10, fake, fake,
+                       2, 1.0, ctypes.byref(o))
+        assert st == tf.TF_E_INVALID and ctx.value is None

@@ -1,0 +1,89 @@
+"""The tf_options the boundary carries beyond the method's inputs: the random
+column order (Algorithm 1 draws each split's columns without replacement), the
+self-tuning strategy, the device-memory hooks and the memory budget.  GPU runs
+against the FP64 oracle through the C ABI."""
+import numpy as np
+import pytest
+
+from gpu_util import note, pair, problem, rel_max
+from oracle import oracle as orc
+
+pytestmark = pytest.mark.gpu
+
+
+def test_random_column_order_matches_the_oracle_rule_f64():
+    from paper_1410_5209_amd import tf
+    dims, K, C, seed = [50, 40, 30], 12, 5, 77
+    note("random column order f64")
+    idx, x, A = problem(310, dims, 4000, K)
+    g, o = pair(dims, idx, x, A, K, 0.3, "f64", col_order=tf.TF_ORDER_RANDOM, seed=seed)
+    for t in range(3):
+        g.sweep(C, 1)
+        order = orc.column_order(seed, t, K)
+        assert np.array_equal(g.col_order(), order), t
+        o.sweep(C, 1, order=order)
+        for n in range(3):
+            assert rel_max(g.factor(n), o.get_factor(n)) < 1e-10, (t, n)
+    gl, _ = g.loss()
+    ol, _ = o.loss()
+    assert abs(gl - ol) <= 1e-9 * ol
+    g.close()
+
+
+@pytest.mark.parametrize("precision,C", [("f64", 4), ("f32", 32)])
+def test_self_tuning_strategy_matches_the_oracle(precision, C):
+    from paper_1410_5209_amd import tf
+    dims, K = [400, 300, 200], 40 if C == 32 else 8
+    note(f"strategy auto {precision} C={C}")
+    idx, x, A = problem(311, dims, 30000, K, dist="zipf", dedupe="drop")
+    g, o = pair(dims, idx, x, A, K, 0.5, precision, strategy=tf.TF_STRATEGY_AUTO)
+    g.sweep(C, 1)
+    o.sweep(C, 1)
+    tol = 1e-10 if precision == "f64" else 1e-3
+    for n in range(3):
+        assert rel_max(g.factor(n), o.get_factor(n)) < tol, n
+    g.split(list(range(3)), 2)      # a narrower split (tuned again when its compute width differs)
+    o.split(list(range(3)), 2)
+    for n in range(3):
+        assert rel_max(g.factor(n), o.get_factor(n)) < tol, n
+    g.close()
+
+
+def test_torch_allocator_hooks_give_identical_results_and_free_everything():
+    import torch
+    from paper_1410_5209_amd import tf
+    from test_gpu_foldin import _gpu_foldin, _requests
+    dims, K = [300, 200, 100], 16
+    note("device memory hooks")
+    idx, x, A = problem(312, dims, 20000, K)
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    runs = []
+    for hooks in (False, True):
+        g, _ = pair(dims, idx, x, A, K, 0.4, "f32", torch_alloc=hooks)
+        if hooks:
+            assert torch.cuda.memory_allocated() > base + 20000 * 4   # the model lives in torch's pool
+        g.sweep(8, 2)
+        ptr, oidx, vals = _requests(dims, 0, [1, 30, 700], 9)
+        rows = _gpu_foldin(g, 0, ptr, oidx, vals, tf.TF_FOLDIN_FULL)
+        runs.append((g.factors(), g.residual(), rows))
+        g.close()
+        torch.cuda.synchronize()
+    for a, b in zip(runs[0][0], runs[1][0]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(runs[0][1], runs[1][1]) and np.array_equal(runs[0][2], runs[1][2])
+    assert torch.cuda.memory_allocated() <= base + 4096   # tensors of this test aside
+
+
+def test_memory_budget_refuses_what_does_not_fit():
+    from paper_1410_5209_amd import tf
+    from paper_1410_5209_amd.model import SparseCP
+    dims, K = [300, 200, 100], 16
+    note("memory budget")
+    idx, x, _ = problem(313, dims, 20000, K)
+    with pytest.raises(tf.TFError) as e:
+        SparseCP(dims, idx, x, K, 0.4, mem_budget=1 << 20)
+    assert e.value.status == tf.TF_E_NOMEM
+    g = SparseCP(dims, idx, x, K, 0.4, mem_budget=64 << 20)
+    g.sweep(8, 1)
+    g.close()

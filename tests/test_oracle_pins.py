@@ -439,3 +439,27 @@ def test_library_init_rule_uses_splitmix_counters():
     A1 = o.get_factor(1)
     assert np.all((A1 >= 0) & (A1 < 0.5))
     assert A1[0, 0] == (orc.splitmix64(seed, 1 + dims[0] * K) >> 11) * 2.0 ** -53 / 2.0
+
+
+def test_random_column_order_is_a_uniform_permutation_from_splitmix():
+    """The random column order (Algorithm 1 draws the columns of each split
+    without replacement): a permutation of 0..K-1 for every sweep; for K = 2
+    the one step swaps unless the top bit of SplitMix64 output 2^62 + 2t + 1 is set
+    (pinned by the published outputs above); for K = 3 all six orders appear
+    about equally often (a shuffle whose index range missed position i
+    would give only the two cyclic ones)."""
+    for K in (1, 2, 7, 100):
+        for t in range(5):
+            order = orc.column_order(12345, t, K)
+            assert sorted(order.tolist()) == list(range(K))
+    for t in range(64):   # j = top bit; j = 1 leaves position 1 in place
+        top = orc.splitmix64(99, (1 << 62) + 2 * t + 1) >> 63
+        assert orc.column_order(99, t, 2).tolist() == ([0, 1] if top else [1, 0])
+    counts = {}
+    n = 6000
+    for t in range(n):
+        key = tuple(orc.column_order(7, t, 3).tolist())
+        counts[key] = counts.get(key, 0) + 1
+    assert len(counts) == 6
+    chi2 = sum((c - n / 6) ** 2 / (n / 6) for c in counts.values())
+    assert chi2 < 25.0   # 5 degrees of freedom: p < 1e-4 beyond this
