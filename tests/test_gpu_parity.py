@@ -448,3 +448,45 @@ def test_factor_block_reads_chosen_rows_and_columns():
                 g.factor_block(1, bad.get("rows"), bad.get("cols"))
             assert e.value.status == tf.TF_E_INVALID
         g.close()
+
+
+def test_non_positive_pivot_is_reported_and_recovered_f64():
+    """A factor row of 1e200 overflows the Gram matrices of the mode-1 rows it
+    meets (B = Inf, so the Cholesky pivots become NaN): the sweep reports
+    TF_E_NUMERIC naming mode 0 and the smallest such row, as the oracle does;
+    those rows keep their values and every other mode-1 row is updated as by
+    the oracle; tf_set_factor + tf_resync then restore a state that sweeps
+    like a fresh oracle."""
+    import re
+    from oracle import oracle as orc
+    from paper_1410_5209_amd import tf
+    dims, K = [40, 30, 20], 4
+    note("non-positive pivot f64")
+    idx, x, A = problem(320, dims, 3000, K, first_zero=False)
+    bad = [a.copy() for a in A]
+    bad[1][3, :] = 1e200
+    g, o = pair(dims, idx, x, bad, K, 0.3, "f64")
+    with pytest.raises(tf.TFError) as e:
+        g.sweep(K, 1)
+    assert e.value.status == tf.TF_E_NUMERIC
+    m = re.search(r"mode (\d+) row (\d+)", str(e.value))
+    with pytest.raises(orc.OracleError) as oe:
+        o.sweep(K, 1)
+    obad = int(re.search(r"bad_row=(\d+)", str(oe.value)).group(1))
+    assert m and int(m.group(1)) == 0 and int(m.group(2)) == obad
+    touched = np.unique(idx[idx[:, 1] == 3, 0])
+    assert int(m.group(2)) == touched.min()
+    G0, O0 = g.factor(0), o.get_factor(0)
+    assert np.array_equal(G0[touched], bad[0][touched])
+    keep = np.setdiff1d(np.arange(dims[0]), touched)
+    assert rel_max(G0[keep], O0[keep]) < 1e-10
+    g.set_factors(A)
+    o2 = orc.Oracle(dims, idx, x, K, 0.3)
+    for n, An in enumerate(A):
+        o2.set_factor(n, An)
+    o2.resync()
+    g.sweep(K, 1)
+    o2.sweep(K, 1)
+    for n in range(3):
+        assert rel_max(g.factor(n), o2.get_factor(n)) < 1e-10, n
+    g.close()
