@@ -77,6 +77,21 @@ def kernel_stats(stats_dir):
         return list(csv.DictReader(f))
 
 
+def timed_launches(stats_dir, n):
+    """Mean duration (us) of the last n accumulation launches in the kernel trace
+    of the stats run (the timed sweeps, after tuning trials and warm-up)."""
+    paths = glob.glob(os.path.join(stats_dir, "**", "*kernel_trace.csv"), recursive=True)
+    if not paths:
+        return None
+    with open(paths[0]) as f:
+        rows = [r for r in csv.DictReader(f) if "k_accum" in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    last = rows[-n:]
+    if not last:
+        return None
+    return sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in last) / len(last) / 1e3
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--stats", required=True)
@@ -90,6 +105,8 @@ def main():
     ap.add_argument("--tcc", default=None,
                     help="counter_collection.csv of a `--pmc TCC_HIT_sum TCC_MISS_sum` run")
     ap.add_argument("--tcc-cmd", default="")
+    ap.add_argument("--timed", type=int, default=0,
+                    help="accumulation launches of the timed sweeps in the stats run")
     ap.add_argument("--last", type=int, default=0,
                     help="average only the last N accumulation launches of each counter run")
     args = ap.parse_args()
@@ -109,7 +126,13 @@ def main():
     acc = [r for r in stats if "k_accum" in r["Name"]]
     calls = sum(int(r["Calls"]) for r in acc)
     avg_us = sum(float(r["TotalDurationNs"]) for r in acc) / max(calls, 1) / 1e3
-    lines += ["", f"All accumulation launches (k_accum*): {calls} calls, average {avg_us:.1f} us per launch."]
+    lines += ["", f"All accumulation launches (k_accum*): {calls} calls, average {avg_us:.1f} us per launch "
+              "(tuning trials included)."]
+    if args.timed:
+        t_us = timed_launches(args.stats, args.timed)
+        if t_us is not None:
+            lines += ["", f"Timed sweeps of the same run (the last {args.timed} accumulation launches of "
+                      f"its kernel trace): average {t_us:.1f} us per launch."]
 
     traffic = None
     if args.fetch and args.write:
