@@ -290,8 +290,11 @@ def main():
         print(json.dumps({"workload": w.name, "precision_compare": res}), flush=True)
         return
     t0 = time.perf_counter()
+    # random order: the library draws the columns of every sweep without
+    # replacement (Algorithm 1), a seeded permutation per sweep
+    order_opt = tf.TF_ORDER_RANDOM if args.col_order == "random" else tf.TF_ORDER_FIXED
     m = SparseCP(dims, idx, x, w.K, w.lam, precision=w.prec, strategy=args.strategy,
-                 lane_nnz=args.lane_nnz, reg_mode=args.reg_mode)
+                 lane_nnz=args.lane_nnz, reg_mode=args.reg_mode, col_order=order_opt)
     torch.cuda.synchronize()
     log(f"tf_init {time.perf_counter() - t0:.1f} s")
 
@@ -318,10 +321,6 @@ def main():
         log(f"autotune: C={C} ({r.tune_ms:.0f} ms)")
 
     def one_sweep(s):
-        # random order: the columns of every sweep are drawn without
-        # replacement (Algorithm 1), as a seeded permutation per sweep
-        if args.col_order == "random":
-            m.set_col_order(synth.column_order(synth.SEED_ORDER, s, w.K))
         m.sweep(C, w.T_in)
 
     for s in range(args.warmup):
