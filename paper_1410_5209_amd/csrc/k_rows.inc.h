@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256) void k_accum(AccumArgs a)
         // (with a.rperm the residual is read from another mode's copy)
         const int32_t *rperm = a.rperm;
         auto load_r = [&](int64_t jj) -> TR {
-            return rperm ? rhat[stream_load(rperm + jj)] : stream_load(rhat + jj);
+            return rperm ? stream_load(rhat + stream_load(rperm + jj)) : stream_load(rhat + jj);
         };
         int32_t ii[NO];
         TR rh = TR(0);

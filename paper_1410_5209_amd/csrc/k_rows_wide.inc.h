@@ -122,8 +122,10 @@ __global__ __launch_bounds__(256) void k_accum_wide(AccumArgs a)
             int32_t bidx[NO];
 #pragma unroll
             for (int l = 0; l < NO; ++l) bidx[l] = lv ? stream_load(a.oidx[l] + jl) : 0;
+            // residuals read through another mode's order are used once: a
+            // streaming load keeps their lines from displacing factor rows in L2
             float brh = 0.f;
-            if (lv) brh = (float)(a.rperm ? rhat[stream_load(a.rperm + jl)] : stream_load(rhat + jl));
+            if (lv) brh = (float)(a.rperm ? stream_load(rhat + stream_load(a.rperm + jl)) : stream_load(rhat + jl));
             float rnew = 0.f;
             const int nstep = (int)((end - s0 + 1) / 2 < 32 ? (end - s0 + 1) / 2 : 32);
             for (int u0 = 0; u0 < nstep; u0 += GS) {
