@@ -316,7 +316,10 @@ typedef struct tf_serve_stats {
 typedef struct tf_server tf_server;
 
 void tf_serve_default_options(tf_serve_opts *opt);
-/* Starts the scheduler and completion threads.  NULL opts = defaults. */
+/* Starts the scheduler and completion threads.  NULL opts = defaults.  The
+ * server reads ctx's factors and allocates its slots through ctx (counted
+ * against tf_options.mem_budget): close it before tf_destroy(ctx), and do not
+ * change the factors while it serves. */
 tf_status tf_serve_open(tf_ctx *ctx, const tf_serve_opts *opts, tf_server **out);
 /* Copies the request (caller may free it on return).  TF_E_BUSY when the
  * queue is full; TF_E_INVALID for m < 0 or a request whose device bytes
