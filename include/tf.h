@@ -61,7 +61,7 @@ typedef int32_t tf_status;
                                 split of each new compute width */
 
 /* Column order of tf_sweep (Algorithm 1 draws each split's columns without
- * replacement; Section 5 keeps a fixed order for CDTF). */
+ * replacement; Section 3.1 keeps a fixed order for CDTF). */
 #define TF_ORDER_FIXED 0     /* the order set by tf_set_col_order (initially
                                 0..K-1): blocks of C consecutive entries */
 #define TF_ORDER_RANDOM 1    /* every tf_sweep first draws a permutation:
@@ -89,7 +89,8 @@ typedef struct tf_options {
     int32_t first_factor_zero; /* 1 (default): A^(1) = 0 so that R = X
                                   (Section 3.1); 0: all factors random */
     int32_t strategy;          /* TF_STRATEGY_* (default TF_STRATEGY_SKEW) */
-    uint64_t seed;             /* factor initialisation seed (default 2) */
+    uint64_t seed;             /* seed of the factor initialisation and of
+                                  TF_ORDER_RANDOM (default 2) */
     void *stream;              /* hipStream_t, NULL = null stream */
     int32_t lane_nnz;          /* SKEW: target nonzeros per lane (0 = 2) */
     int32_t split_threshold;   /* SKEW: rows longer than this are split
