@@ -490,3 +490,29 @@ def test_non_positive_pivot_is_reported_and_recovered_f64():
     for n in range(3):
         assert rel_max(g.factor(n), o2.get_factor(n)) < 1e-10, n
     g.close()
+
+
+@pytest.mark.parametrize("precision,share", [("f32", "own"), ("f32", "shared"), ("bf16", "own")])
+def test_wide_split_with_each_residual_placement(precision, share):
+    """C = 32 with every mode keeping its own R-hat (each mode's first pass reads
+    the split-start segments of the modes already updated) or all reading mode
+    1's copy, over two inner iterations and a following narrower split."""
+    from paper_1410_5209_amd import tf
+    mode = {"own": tf.TF_RESID_OWN, "shared": tf.TF_RESID_SHARED}[share]
+    dims, K = [300, 250, 200, 150], 40
+    note(f"wide {precision} placement {share}")
+    idx, x, A = problem(340, dims, 30000, K, dist="zipf", dedupe="drop")
+    g, o = pair(dims, idx, x, A, K, 0.5, precision, resid_share=mode, split_threshold=512,
+                chunk_nnz=128)
+    for cols, T_in in ((list(range(32)), 2), (list(range(32, 40)), 1), (list(range(5, 37)), 1)):
+        g.split(cols, T_in)
+        o.split(cols, T_in)
+    gl, gr = g.loss()
+    ol, orr = o.loss()
+    if precision == "f32":
+        assert abs(gl - ol) <= 1e-4 * ol and abs(gr - orr) <= 1e-4 * orr, (gl, ol)
+        for n in range(4):
+            assert rel_max(g.factor(n), o.get_factor(n)) < 1e-3, n
+    else:
+        assert abs(gr - orr) <= 5e-3 * orr and abs(gl - ol) <= 1e-2 * ol, (gl, ol)
+    g.close()
