@@ -516,3 +516,46 @@ def test_wide_split_with_each_residual_placement(precision, share):
     else:
         assert abs(gr - orr) <= 5e-3 * orr and abs(gl - ol) <= 1e-2 * ol, (gl, ol)
     g.close()
+
+
+WIDTH_CASES = [
+    # precision, N, C, dist
+    ("f32", 3, 1, "uniform"), ("f32", 3, 5, "zipf"), ("f32", 6, 12, "uniform"),
+    ("f32", 7, 32, "zipf"), ("bf16", 4, 4, "zipf"), ("bf16", 3, 16, "uniform"),
+    ("f64", 6, 3, "zipf"), ("f64", 3, 12, "uniform"),
+]
+
+
+@pytest.mark.parametrize("precision,N,C,dist", WIDTH_CASES)
+def test_kernel_widths_and_mode_counts(precision, N, C, dist):
+    """Compute widths and numbers of other modes not covered above (each an
+    instantiation of its own), on uniform and skewed tensors with chunked
+    rows, one split of two inner iterations against the oracle."""
+    dims = [60, 50, 45, 40, 35, 30, 25][:N]
+    K = max(C + 3, 8)
+    note(f"widths {precision} N={N} C={C} {dist}")
+    idx, x, A = problem(350 + N + C, dims, 12000, K, dist=dist,
+                        dedupe="drop" if dist == "zipf" else "distinct", first_zero=False)
+    # with five or more other modes, products of U(0,1)/sqrt(K) entries are so
+    # small that lambda would drive every row towards zero within one split
+    # (values below FP32's range); scale the factors to mean 1 and ease lambda
+    scale = (1.0 / np.mean(A[1])) ** 0.5 if N > 4 else 1.0
+    A = [a * scale for a in A]
+    lam = 0.4 if N <= 4 else 0.02
+    g, o = pair(dims, idx, x, A, K, lam, precision, split_threshold=256, chunk_nnz=64)
+    cols = list(range(K - C, K))
+    g.split(cols, 2)
+    o.split(cols, 2)
+    gl, gr = g.loss()
+    ol, orr = o.loss()
+    if precision == "f64":
+        for n in range(N):
+            assert rel_max(g.factor(n), o.get_factor(n)) < 1e-10, n
+        assert abs(gl - ol) <= 1e-9 * ol
+    elif precision == "f32":
+        for n in range(N):
+            assert rel_max(g.factor(n), o.get_factor(n)) < 1e-3, n
+        assert abs(gl - ol) <= 1e-4 * ol and abs(gr - orr) <= 1e-4 * orr
+    else:
+        assert abs(gr - orr) <= 5e-3 * orr and abs(gl - ol) <= 1e-2 * ol, (gl, ol)
+    g.close()
