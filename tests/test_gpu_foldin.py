@@ -232,3 +232,31 @@ def test_serving_replay_poisson_and_close_with_work_in_flight():
         tf.tf_serve_submit(srv, tf.make_request(oi, va))
     tf.tf_serve_close(srv)
     g.close()
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_foldin_bf16_factors_and_k_above_the_full_rank_limit(method):
+    """BF16 factor storage (the oracle holds the same BF16 values), K = 48, plus
+    CDTF fold-in at K = 160, where it walks the entries instead of a Gram."""
+    from oracle import oracle as orc
+    from paper_1410_5209_amd.model import SparseCP
+    for prec, K in (("bf16", 48), ("f32", 160)):
+        if method == 0 and K > 128:
+            continue        # full rank stops at K = 128 (tested elsewhere)
+        dims = [300, 200, 150]
+        note(f"foldin {prec} K={K} method={method}")
+        idx, x, A = problem(36, dims, 20000, K, first_zero=False)
+        g = SparseCP(dims, idx, x, K, 0.5, precision=prec)
+        g.set_factors(A)
+        o = orc.Oracle(dims, idx, x, K, 0.5)
+        for n in range(3):
+            o.set_factor(n, g.factor(n))     # the values the GPU holds
+        sizes = [1, 7, 64, 900, 3000]
+        ptr, oidx, vals = _requests(dims, 1, sizes, 8)
+        rows = _gpu_foldin(g, 1, ptr, oidx, vals, method)
+        for q in range(len(sizes)):
+            sl = slice(ptr[q], ptr[q + 1])
+            want = o.foldin_full(1, oidx[sl], vals[sl]) if method == 0 else \
+                o.foldin_cdtf(1, oidx[sl], vals[sl], 3)
+            assert rel_max(rows[q], want) < 1e-4, (prec, K, q)
+        g.close()
