@@ -260,3 +260,45 @@ def test_foldin_bf16_factors_and_k_above_the_full_rank_limit(method):
                 o.foldin_cdtf(1, oidx[sl], vals[sl], 3)
             assert rel_max(rows[q], want) < 1e-4, (prec, K, q)
         g.close()
+
+
+def test_serving_through_torch_allocator_and_context_budget():
+    """Serving slots come from the context's allocator: with torch's caching
+    allocator as the hook the served rows equal tf_foldin's, and a context
+    memory budget too small for the slots makes tf_serve_open fail with
+    TF_E_NOMEM and leaves the context usable."""
+    import torch
+    from paper_1410_5209_amd import tf
+    from paper_1410_5209_amd.model import SparseCP
+    note("serving through the torch allocator")
+    dims, K = [3000, 2000, 1500], 24
+    idx, x, A = problem(37, dims, 60000, K, first_zero=False)
+    sizes = list(synth.zipf_ints(11, 500, 40, 1.1, 2000))
+    ptr, oidx, vals = _requests(dims, 0, sizes, 12)
+    g = SparseCP(dims, idx, x, K, 1.0, torch_alloc=True)
+    g.set_factors(A)
+    want = _gpu_foldin(g, 0, ptr, oidx, vals, 0)
+    before = torch.cuda.memory_allocated()
+    srv = tf.tf_serve_open(g.ctx, tf.tf_serve_default_options(streams=2, mem_budget=64 << 20))
+    assert torch.cuda.memory_allocated() >= before + (64 << 20)   # slots in torch's pool
+    keep, tickets = [], []
+    for q in range(len(sizes)):
+        sl = slice(ptr[q], ptr[q + 1])
+        oi, va = np.ascontiguousarray(oidx[sl]), np.ascontiguousarray(vals[sl])
+        keep.append((oi, va))
+        tickets.append(tf.tf_serve_submit(srv, tf.make_request(oi, va)))
+    for q, t in enumerate(tickets):
+        row, _ = tf.tf_serve_wait(srv, t, K)
+        assert np.array_equal(row, want[q])
+    tf.tf_serve_close(srv)
+    assert torch.cuda.memory_allocated() <= before
+    g.close()
+
+    g = SparseCP(dims, idx, x, K, 1.0, mem_budget=48 << 20)
+    g.set_factors(A)
+    with pytest.raises(tf.TFError) as e:
+        tf.tf_serve_open(g.ctx, tf.tf_serve_default_options(streams=2, mem_budget=64 << 20))
+    assert e.value.status == tf.TF_E_NOMEM
+    got = _gpu_foldin(g, 0, ptr, oidx, vals, 0)
+    assert np.array_equal(got, want)
+    g.close()
