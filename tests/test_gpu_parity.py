@@ -559,3 +559,21 @@ def test_kernel_widths_and_mode_counts(precision, N, C, dist):
     else:
         assert abs(gr - orr) <= 5e-3 * orr and abs(gl - ol) <= 1e-2 * ol, (gl, ol)
     g.close()
+
+
+def test_wide_split_weighted_lambda_f32():
+    """The 32-column kernels and solve with the weighted regulariser
+    lambda |Omega_i| (Section 5.1.3), on skewed rows with chunks."""
+    dims, K = [400, 300, 200], 40
+    note("wide f32 weighted lambda")
+    idx, x, A = problem(360, dims, 30000, K, dist="zipf", dedupe="drop", first_zero=False)
+    g, o = pair(dims, idx, x, A, K, 0.05, "f32", reg_mode=1, split_threshold=512, chunk_nnz=128)
+    for cols in (list(range(32)), list(range(8, 40))):
+        g.split(cols, 1)
+        o.split(cols, 1)
+    for n in range(3):
+        assert rel_max(g.factor(n), o.get_factor(n)) < 1e-3, n
+    gl, gr = g.loss()
+    ol, orr = o.loss()
+    assert abs(gl - ol) <= 1e-4 * ol and abs(gr - orr) <= 1e-4 * orr
+    g.close()
