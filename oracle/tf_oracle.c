@@ -300,51 +300,86 @@ static int check_cols(const or_ctx *c, int ncols, const int32_t *cols)
     return OR_OK;
 }
 
-/* One split of Algorithm 1 for the given columns k_1..k_C:
- *   compute R-hat (rhat = r + sum_c prod_n a),
- *   T_in times: for n = 1..N: update every row of mode n by eq. (SALS),
- *   update R by eq. (SALS_R) (r = rhat - sum_c prod_n a).               */
+/* R-hat of a split (Section 3.1): the residual with the split's columns'
+ * current contribution added back, i.e. x minus the model of every column
+ * outside the split. */
+static void form_rhat(const or_ctx *c, int ncols, const int32_t *cols, double *rhat)
+{
+    for (int64_t j = 0; j < c->nnz; ++j) rhat[j] = c->r[j] + model_cols(c, j, ncols, cols);
+}
+
+/* Every row of mode n replaced by its eq. (SALS) minimiser against rhat.
+ * Rows of one mode read only the other modes (Section 3.3), so they are
+ * independent.  A row whose Cholesky meets a non-positive pivot keeps its
+ * value; the smallest such row is returned (-1 if none). */
+static int64_t update_mode(or_ctx *c, int n, int ncols, const int32_t *cols, const double *rhat)
+{
+    int64_t I = c->dims[n];
+    int64_t bad = -1;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < I; ++i) {
+        double a[64];
+        double *ap = ncols <= 64 ? a : (double *)malloc((size_t)ncols * sizeof(double));
+        if (row_solve(c, n, i, ncols, cols, rhat, NULL, ap) != 0) {
+#pragma omp critical
+            { if (bad < 0 || i < bad) bad = i; }
+        } else {
+            for (int q = 0; q < ncols; ++q) c->A[n][i * c->K + cols[q]] = ap[q];
+        }
+        if (ap != a) free(ap);
+    }
+    return bad;
+}
+
+/* R after a split, eq. (SALS_R): rhat minus the split's columns' new
+ * contribution. */
+static void residual_after_split(or_ctx *c, int ncols, const int32_t *cols, const double *rhat)
+{
+    for (int64_t j = 0; j < c->nnz; ++j) c->r[j] = rhat[j] - model_cols(c, j, ncols, cols);
+}
+
+/* One split of serial SALS (Algorithm 1) on the columns cols[0..ncols):
+ * R-hat, then T_in inner iterations each replacing the rows of modes
+ * 1..N in turn, then R by eq. (SALS_R).  A non-positive pivot ends the
+ * inner iterations after the mode where it happened (that mode's other rows
+ * are updated); R is still brought up to date, so the state stays
+ * consistent. */
 int or_split(or_ctx *c, int ncols, const int32_t *cols, int T_in)
 {
     if (check_cols(c, ncols, cols) != OR_OK || T_in < 1) return OR_E_INVALID;
     double *rhat = (double *)malloc((size_t)(c->nnz > 0 ? c->nnz : 1) * sizeof(double));
     if (!rhat) return OR_E_NOMEM;
-    for (int64_t j = 0; j < c->nnz; ++j) rhat[j] = c->r[j] + model_cols(c, j, ncols, cols);
-
+    form_rhat(c, ncols, cols, rhat);
     int status = OR_OK;
     for (int it = 0; it < T_in && status == OR_OK; ++it) {
         for (int n = 0; n < c->N && status == OR_OK; ++n) {
-            int64_t I = c->dims[n];
-            int64_t bad = -1;
-#pragma omp parallel for schedule(dynamic, 256)
-            for (int64_t i = 0; i < I; ++i) {
-                double a[64];
-                double *ap = ncols <= 64 ? a : (double *)malloc((size_t)ncols * sizeof(double));
-                if (row_solve(c, n, i, ncols, cols, rhat, NULL, ap) != 0) {
-#pragma omp critical
-                    { if (bad < 0 || i < bad) bad = i; }
-                } else {
-                    for (int q = 0; q < ncols; ++q) c->A[n][i * c->K + cols[q]] = ap[q];
-                }
-                if (ap != a) free(ap);
-            }
+            int64_t bad = update_mode(c, n, ncols, cols, rhat);
             if (bad >= 0) { c->bad_row = bad; c->bad_mode = n; status = OR_E_NUMERIC; }
         }
     }
-    for (int64_t j = 0; j < c->nnz; ++j) c->r[j] = rhat[j] - model_cols(c, j, ncols, cols);
+    residual_after_split(c, ncols, cols, rhat);
     free(rhat);
     return status;
 }
 
-/* One outer iteration of Algorithm 1: ceil(K/C) splits over the column order
- * `order` (a permutation of 0..K-1), C columns per split (Q3/Q4). */
+/* Block s of an outer iteration over K columns in blocks of C (reading Q4:
+ * ceil(K/C) blocks, the last one shorter when C does not divide K). */
+static int block_width(int K, int C, int s)
+{
+    int start = s * C;
+    return K - start < C ? K - start : C;
+}
+
+/* One outer iteration of serial SALS (Algorithm 1): the column order
+ * `order` (a permutation of 0..K-1) taken block by block, one split per
+ * block.  Stops at the first split that meets a non-positive pivot. */
 int or_sweep(or_ctx *c, int C, int T_in, const int32_t *order)
 {
     if (C < 1 || C > c->K || T_in < 1) return OR_E_INVALID;
     if (check_cols(c, c->K, order) != OR_OK) return OR_E_INVALID;
-    for (int s = 0; s < c->K; s += C) {
-        int w = (c->K - s) < C ? (c->K - s) : C;
-        int rc = or_split(c, w, order + s, T_in);
+    int nblocks = (c->K + C - 1) / C;
+    for (int s = 0; s < nblocks; ++s) {
+        int rc = or_split(c, block_width(c->K, C, s), order + (int64_t)s * C, T_in);
         if (rc != OR_OK) return rc;
     }
     return OR_OK;

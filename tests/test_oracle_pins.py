@@ -170,6 +170,35 @@ def test_row_update_matches_dense_least_squares_on_current_state():
         assert rel(o.row_update(0, i, cols), want[0][i, cols]) < 1e-10
 
 
+@pytest.mark.parametrize("reg", [0, 1])
+def test_sweep_walks_the_order_in_blocks_of_dense_least_squares_splits(reg):
+    """Algorithm 1's outer iteration: the column order is taken in ceil(K/C)
+    blocks of C columns, the last block shorter when C does not divide K
+    (reading Q4), and every block is one split.  K = 7, C = 3 gives blocks of
+    3, 3 and 1 columns of a non-identity order; each is checked against the
+    dense least-squares split applied to the factors the previous block left
+    (its target x minus the model of the columns outside the block, recomputed
+    from scratch, so the residual the oracle carries between splits is pinned
+    too).  Over two sweeps, T_in = 2."""
+    dims = [6, 5, 7]
+    K, C, T_in = 7, 3, 2
+    lam = 0.02 if reg else 0.35    # weighted: lambda_i = lambda |Omega_i| (~15 entries a row)
+    order = [4, 0, 6, 2, 5, 1, 3]
+    idx, x, A = tiny_problem(91 + reg, dims, 110, K)
+    o = make_oracle(dims, idx, x, A, K, lam, reg)
+    want = [a.copy() for a in A]
+    for _ in range(2):
+        o.sweep(C, T_in, order)
+        blocks = [order[s:s + C] for s in range(0, K, C)]
+        assert [len(b) for b in blocks] == [3, 3, 1]
+        for cols in blocks:
+            want = brute_split(dims, idx, x, want, cols, T_in, lam, reg)
+        for n in range(3):
+            assert np.max(np.abs(want[n])) > 0.05              # not shrunk to zero
+            assert rel(o.get_factor(n), want[n]) < 1e-9, n
+        assert np.max(np.abs(o.residual() - (x - recon(dims, idx, want)))) < 1e-9 * np.max(np.abs(x))
+
+
 # ------------------------------------------------------- P3: CDTF closed form
 
 def test_cdtf_equals_scalar_closed_form():
