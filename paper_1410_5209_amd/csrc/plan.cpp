@@ -7,7 +7,8 @@
 #include <algorithm>
 #include <numeric>
 
-#include "tf_internal.h"
+#include "plan.h"
+#include "../../include/tf.h"
 
 namespace tfk {
 
@@ -30,7 +31,7 @@ void plan_rows(const int64_t *rowptr, int64_t I, int strategy, int lane_nnz, int
 
     if (strategy == TF_STRATEGY_PLAIN) {
         for (int64_t i = 0; i < I; ++i) {
-            if (cnt(i) == 0) { out->empty_rows += 1; continue; }
+            if (cnt(i) == 0) { out->empty_rows += 1; out->empty.push_back((int32_t)i); continue; }
             out->tasks.push_back(Task{64, (int32_t)out->items.size(), 1, 0});
             out->items.push_back((int32_t)i);
             out->rows_by_lanes[6] += 1;
@@ -43,7 +44,7 @@ void plan_rows(const int64_t *rowptr, int64_t I, int strategy, int lane_nnz, int
     std::vector<int32_t> split;
     for (int64_t i = 0; i < I; ++i) {
         const int64_t c = cnt(i);
-        if (c == 0) { out->empty_rows += 1; continue; }
+        if (c == 0) { out->empty_rows += 1; out->empty.push_back((int32_t)i); continue; }
         if (c > split_threshold) { split.push_back((int32_t)i); continue; }
         const int G = lanes_for(c, lane_nnz);
         bucket[__builtin_ctz(G)].push_back((int32_t)i);
@@ -86,7 +87,7 @@ int pick_cp(int C, int prec)
 {
     static const int f64[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
     static const int f32[] = {1, 2, 4, 5, 8, 10, 12, 16, 32};
-    if (prec == P_F64) {
+    if (prec == 0) {
         for (int v : f64) if (v >= C) return v;
     } else {
         for (int v : f32) if (v >= C) return v;

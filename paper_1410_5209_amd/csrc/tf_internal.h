@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/tf.h"
+#include "plan.h"
 
 namespace tfk {
 
@@ -30,42 +31,8 @@ constexpr int kMaxModes = 8;
 __host__ __device__ constexpr int gram_entries(int CP) { return CP * (CP + 1) / 2 + CP; }
 __host__ __device__ constexpr int gram_stride(int CP) { return (gram_entries(CP) + 3) & ~3; }
 
-// Compute widths the row kernels are instantiated for; C is padded up to the
-// next one (padded slab columns hold zeros, which leaves the solution of the
-// real columns unchanged and the padded ones at zero).
-int pick_cp(int C, int prec);
-
 // ---------------------------------------------------------------- work plan
-// A task is one wavefront's unit of work.
-//   kind 0: up to 64/G rows, G lanes each (items[base .. base+count))
-//   kind 1: one chunk of a long row (chunks[base]), 64 lanes
-struct Task {
-    int32_t G;
-    int32_t base;
-    int32_t count;
-    int32_t kind;
-};
-struct Chunk {
-    int32_t row;
-    int32_t beg;
-    int32_t end;
-    int32_t slot;
-};
-
-constexpr int64_t kMaxChunksPerRow = 1024;
-
-struct HostPlan {
-    std::vector<Task> tasks;
-    std::vector<int32_t> items;
-    std::vector<Chunk> chunks;
-    std::vector<int32_t> split_rows;     // rows cut into chunks
-    std::vector<int32_t> split_chunk_ptr;// chunk range per split row (size+1)
-    int64_t empty_rows = 0;
-    int64_t rows_by_lanes[7] = {0, 0, 0, 0, 0, 0, 0};
-};
-
-void plan_rows(const int64_t *rowptr, int64_t I, int strategy, int lane_nnz, int split_threshold,
-               int chunk_nnz, HostPlan *out);
+// (Task, Chunk, HostPlan, plan_rows, pick_cp: plan.h)
 
 // ---------------------------------------------------------------- kernel args
 struct AccumArgs {
