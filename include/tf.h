@@ -168,7 +168,11 @@ const char *tf_last_error(const tf_ctx *ctx);
  * 17..32 (FP32/BF16; run as 32 columns with zero padding); C = 0 uses the
  * width chosen by tf_autotune.  T_in >= 1.  Blocks until done.
  * TF_E_NUMERIC: a pivot was not positive; the message names the mode and
- * row; that row keeps its previous value and the state stays consistent.
+ * the smallest such row of the first mode pass that met one.  The other rows
+ * of that pass are updated, those rows keep their previous values, and no
+ * factor changes after that pass (the rest of the split and the later splits
+ * only keep R consistent), so the state equals that of Algorithm 1 stopped
+ * after the failing pass.
  * TF_E_STATE: factors were set without tf_resync.
  */
 tf_status tf_sweep(tf_ctx *ctx, int32_t C, int32_t T_in);
@@ -304,7 +308,10 @@ typedef struct tf_req_stats {
     double latency_us;     /* submit -> result on the host */
     double queue_us;       /* submit -> batch launched */
     int32_t batch_size;    /* requests in its batch */
-    int32_t status;        /* TF_OK or TF_E_NUMERIC */
+    int32_t status;        /* TF_OK; TF_E_NUMERIC (a non-positive pivot: the
+                              row is 0); TF_E_DEVICE (a HIP call of its batch
+                              failed: the row is NaN, tf_serve_last_error says
+                              which call) */
 } tf_req_stats;
 
 typedef struct tf_serve_stats {
@@ -312,6 +319,7 @@ typedef struct tf_serve_stats {
     double p50_us, p90_us, p99_us, p999_us, max_us, mean_us;
     double solves_per_s;   /* completed / (last completion - first submit) */
     double mean_batch;
+    int64_t failed;        /* completed with TF_E_DEVICE */
 } tf_serve_stats;
 
 typedef struct tf_server tf_server;
@@ -327,7 +335,9 @@ tf_status tf_serve_open(tf_ctx *ctx, const tf_serve_opts *opts, tf_server **out)
  * exceed one slot's share of the budget.  Thread-safe. */
 tf_status tf_serve_submit(tf_server *srv, const tf_request *req, uint64_t *ticket);
 /* Blocks until the ticket's row is done; h_row host[K] (may be NULL), st may
- * be NULL.  A ticket can be waited once.  Thread-safe. */
+ * be NULL.  A ticket can be waited once.  Returns the request's status
+ * (tf_req_stats.status).  Each request's status is its own: a failed
+ * neighbour in the same batch does not change it.  Thread-safe. */
 tf_status tf_serve_wait(tf_server *srv, uint64_t ticket, double *h_row, tf_req_stats *st);
 /* Load generator: submits reqs[i] at h_arrival_s[i] seconds after the call
  * (non-decreasing), retrying while the queue is full; tickets[i] receives
@@ -339,6 +349,14 @@ tf_status tf_serve_report(tf_server *srv, tf_serve_stats *out);
 tf_status tf_serve_reset_stats(tf_server *srv);
 /* Waits for queued and in-flight requests, then stops the threads. */
 void tf_serve_close(tf_server *srv);
+/* Message of the last batch that failed with TF_E_DEVICE ("" if none); the
+ * string stays valid until the calling thread's next call of this function. */
+const char *tf_serve_last_error(tf_server *srv);
+/* Test hook: the next `nbatches` batches fail at their launch step as if
+ * the fold-in launch had returned an error (no kernel runs for them, the
+ * GPU is not disturbed), so that the error path can be exercised.
+ * TF_E_INVALID for nbatches < 0. */
+tf_status tf_serve_inject_fault(tf_server *srv, int32_t nbatches);
 
 /* ------------------------------------------------------------------ */
 /* Kernel timing: HIP events around every launch of the row-accumulation

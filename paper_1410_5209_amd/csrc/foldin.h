@@ -21,6 +21,7 @@ struct FoldArgs {
     int32_t sweeps;
     unsigned long long *bad;      // first bad entry (validation)
     unsigned long long *bad_req;  // first request whose Cholesky failed
+    int32_t *req_status;          // NULL, or out nreq: TF_OK / TF_E_NUMERIC per request
     // full rank: the entries of request q are cut into chunks of
     // kFoldChunkEntries; chunk_first[q] .. chunk_first[q + 1] - 1 are its
     // chunks, chunk_req[c] the request of chunk c; gpart holds one partial

@@ -162,6 +162,7 @@ __global__ __launch_bounds__(256) void k_fold_full(FoldArgs a)
     const int tid = threadIdx.x;
     if (m == 0) {
         for (int k = tid; k < K; k += 256) out[k] = 0.0;
+        if (tid == 0 && a.req_status) a.req_status[q] = TF_OK;
         return;
     }
     // LDS: packed lower triangle L (K(K+1)/2 doubles), rhs (K doubles)
@@ -212,6 +213,7 @@ __global__ __launch_bounds__(256) void k_fold_full(FoldArgs a)
         }
     }
     __syncthreads();
+    if (tid == 0 && a.req_status) a.req_status[q] = failed ? TF_E_NUMERIC : TF_OK;
     if (failed) {
         if (tid == 0) atomicMin(a.bad_req, (unsigned long long)q);
         for (int k = tid; k < K; k += 256) out[k] = 0.0;
@@ -255,6 +257,7 @@ __global__ __launch_bounds__(256) void k_fold_cdtf(FoldArgs a)
     const int64_t m = a.req_ptr[q + 1] - a.req_ptr[q];
     double *out = a.rows + (int64_t)q * K;
     const int tid = threadIdx.x;
+    if (tid == 0 && a.req_status) a.req_status[q] = TF_OK;   // no pivots in the C = 1 update
     if (m == 0) {
         for (int k = tid; k < K; k += 256) out[k] = 0.0;
         return;
@@ -301,6 +304,7 @@ __global__ __launch_bounds__(256) void k_fold_cdtf_entries(FoldArgs a)
     double *out = a.rows + (int64_t)q * K;
     const int tid = threadIdx.x;
     double *av = smem;           // K
+    if (tid == 0 && a.req_status) a.req_status[q] = TF_OK;   // no pivots in the C = 1 update
     if (m == 0) {
         for (int k = tid; k < K; k += 256) out[k] = 0.0;
         return;

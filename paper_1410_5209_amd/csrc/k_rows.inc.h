@@ -330,27 +330,17 @@ __host__ __device__ constexpr int upper_index(int CP, int c1, int c2)
     return c1 * CP - c1 * (c1 - 1) / 2 + (c2 - c1);
 }
 
+// Solve of one row: (B + lambda_i I) a = c from its Gram record g, written
+// to o in the storage type; false (and nothing written) for a non-positive
+// pivot.
 template <int PREC, int CP>
-__global__ __launch_bounds__(256) void k_solve(SolveArgs a)
+__device__ __forceinline__ bool solve_row(const typename Types<PREC>::TA *g, double lam,
+                                          typename Types<PREC>::TS *o)
 {
     using TS = typename Types<PREC>::TS;
-    using TA = typename Types<PREC>::TA;
-    constexpr int NEP = gram_stride(CP);
     constexpr int NT = CP * (CP + 1) / 2;
-
-    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= a.I) return;
-    const int64_t cnt = (int64_t)a.rowptr[row + 1] - a.rowptr[row];
-    TS *o = reinterpret_cast<TS *>(a.W) + row * a.ld;
-    if (cnt == 0) {  // a row with no observed entries is set to zero
-#pragma unroll
-        for (int c = 0; c < CP; ++c) o[c] = store_cast<TS>(0.0);
-        return;
-    }
-    const TA *g = reinterpret_cast<const TA *>(a.gram) + row * NEP;
     double L[NT];   // packed lower triangle, L(i, k) at i*(i+1)/2 + k
     double y[CP];
-    const double lam = a.reg_mode ? a.lambda * (double)cnt : a.lambda;
 #pragma unroll
     for (int i = 0; i < CP; ++i) {
 #pragma unroll
@@ -375,10 +365,7 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs a)
             L[i * (i + 1) / 2 + jj] = s / ljj;
         }
     }
-    if (!ok) {
-        atomicMin(a.bad, (unsigned long long)row);
-        return;
-    }
+    if (!ok) return false;
 #pragma unroll
     for (int i = 0; i < CP; ++i) {
         double s = y[i];
@@ -395,6 +382,31 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs a)
     }
 #pragma unroll
     for (int c = 0; c < CP; ++c) o[c] = store_cast<TS>(y[c]);
+    return true;
+}
+
+template <int PREC, int CP>
+__global__ __launch_bounds__(256) void k_solve(SolveArgs a)
+{
+    using TS = typename Types<PREC>::TS;
+    using TA = typename Types<PREC>::TA;
+    constexpr int NEP = gram_stride(CP);
+    if (pass_halted(a.flags)) return;   // uniform: no factor changes after a failed pass
+
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row < a.I) {
+        const int64_t cnt = (int64_t)a.rowptr[row + 1] - a.rowptr[row];
+        TS *o = reinterpret_cast<TS *>(a.W) + row * a.ld;
+        if (cnt == 0) {  // a row with no observed entries is set to zero
+#pragma unroll
+            for (int c = 0; c < CP; ++c) o[c] = store_cast<TS>(0.0);
+        } else {
+            const TA *g = reinterpret_cast<const TA *>(a.gram) + row * NEP;
+            const double lam = a.reg_mode ? a.lambda * (double)cnt : a.lambda;
+            if (!solve_row<PREC, CP>(g, lam, o)) atomicMin(a.bad, (unsigned long long)row);
+        }
+    }
+    pass_latch(a.flags, a.nmodes);
 }
 
 // Sum of the chunk partials of each split row into the row's Gram record.

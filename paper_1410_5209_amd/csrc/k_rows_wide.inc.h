@@ -231,6 +231,7 @@ __global__ __launch_bounds__(256) void k_solve_wide(SolveArgs a)
     // per row: first the staged Gram record, then the columns of L below the
     // diagonal (column j at colofs(j), rows j+1..31)
     __shared__ __align__(16) double lt[8][LT];
+    if (pass_halted(a.flags)) return;   // uniform: no factor changes after a failed pass
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int half = lane >> 5;
@@ -327,17 +328,16 @@ __global__ __launch_bounds__(256) void k_solve_wide(SolveArgs a)
 
     const unsigned long long bad = __ballot(!ok);
     const bool row_bad = ((bad >> (32 * half)) & 0xffffffffull) != 0ull;
-    if (!valid) return;
-    TS *o = reinterpret_cast<TS *>(a.W) + row * a.ld;
-    if (!live) {
-        o[i] = store_cast<TS>(0.0);
-        return;
+    if (valid) {
+        TS *o = reinterpret_cast<TS *>(a.W) + row * a.ld;
+        if (!live) o[i] = store_cast<TS>(0.0);
+        else if (row_bad) {
+            if (i == 0) atomicMin(a.bad, (unsigned long long)row);
+        } else {
+            o[i] = store_cast<TS>(c);
+        }
     }
-    if (row_bad) {
-        if (i == 0) atomicMin(a.bad, (unsigned long long)row);
-        return;
-    }
-    o[i] = store_cast<TS>(c);
+    pass_latch(a.flags, a.nmodes);
 }
 
 }  // namespace tfk

@@ -55,6 +55,7 @@ size_t batch_bytes(int N, int K, int prec, int method, int64_t nreq, int64_t tot
     if (!fold_uses_gram(K)) b += align256((size_t)total * 8);     // r (CDTF, large K)
     b += align256((size_t)nc * fold_gram_stride(K) * ta_bytes(prec));  // partial Grams
     b += align256((size_t)nreq * K * 8);                          // rows
+    b += align256((size_t)nreq * 4);                              // per-request status
     b += 256;                                                     // flags
     return b;
 }
@@ -69,6 +70,7 @@ struct Arena {
     double *r;
     void *gpart;
     double *rows;
+    int32_t *status;
     unsigned long long *flags;
 };
 
@@ -88,6 +90,7 @@ Arena carve(void *base, int N, int K, int prec, int method, int64_t nreq, int64_
     if (!fold_uses_gram(K)) { a.r = reinterpret_cast<double *>(p); p += align256((size_t)total * 8); }
     a.gpart = p; p += align256((size_t)nc * fold_gram_stride(K) * ta_bytes(prec));
     a.rows = reinterpret_cast<double *>(p); p += align256((size_t)nreq * K * 8);
+    a.status = reinterpret_cast<int32_t *>(p); p += align256((size_t)nreq * 4);
     a.flags = reinterpret_cast<unsigned long long *>(p);
     return a;
 }
@@ -112,6 +115,7 @@ FoldArgs fold_args(const tf_ctx *c, int mode, const Arena &ar, int64_t nreq, int
     a.sweeps = sweeps;
     a.bad = ar.flags;
     a.bad_req = ar.flags + 1;
+    a.req_status = ar.status;
     a.chunk_first = ar.chunk_first;
     a.chunk_req = ar.chunk_req;
     a.gpart = ar.gpart;
@@ -147,11 +151,12 @@ struct SSlot {
     hipEvent_t ev = nullptr;
     void *dev = nullptr;
     char *hin = nullptr;       // pinned staging of inputs
-    double *hout = nullptr;    // pinned rows
-    unsigned long long *hflags = nullptr;
+    char *hout = nullptr;      // pinned rows, then per-request status words
     std::vector<SReq *> batch;
     bool busy = false;         // owned by a batch (set by scheduler)
     bool launched = false;     // work enqueued, completer may wait
+    bool failed = false;       // a HIP call of the batch failed: no row is valid
+    std::string fail_msg;
     std::thread completer;
 };
 
@@ -173,6 +178,8 @@ struct tf_server {
     clk::time_point t_first, t_last;
     int64_t batches = 0, busy_rejects = 0, max_queue = 0;
     double batch_sum = 0.0;
+    int64_t failed = 0;        // requests completed with TF_E_DEVICE
+    std::atomic<int32_t> inject{0};  // batches left to fail on purpose (tf_serve_inject_fault)
     std::string err;
 };
 
@@ -187,6 +194,9 @@ size_t req_bytes(const tf_server *s, int64_t m)
            chunks * (4 + (size_t)fold_gram_stride(c->K) * ta_bytes(c->prec));
 }
 
+// Stage and enqueue one batch on the slot's stream.  Every HIP call is
+// checked; on a failure the batch is marked failed (its requests complete
+// with TF_E_DEVICE and no row is read back) and the message is kept.
 void run_batch(tf_server *s, SSlot &slot)
 {
     tf_ctx *c = s->ctx;
@@ -218,14 +228,31 @@ void run_batch(tf_server *s, SSlot &slot)
     }
     Arena ar = carve(slot.dev, N, K, c->prec, s->o.method, nreq, total);
     const size_t in_bytes = (size_t)((char *)(hv + total) - slot.hin);
-    (void)hipMemcpyAsync(ar.req_ptr, slot.hin, in_bytes, hipMemcpyHostToDevice, slot.st);
-    (void)hipMemsetAsync(ar.flags, 0xff, 2 * sizeof(unsigned long long), slot.st);
-    FoldArgs a = fold_args(c, s->o.mode, ar, nreq, s->o.sweeps);
-    a.nchunks = (int32_t)nchunks;
-    (void)launch_fold_compute(c->prec, a, total, s->o.method, slot.st);
-    (void)hipMemcpyAsync(slot.hout, ar.rows, (size_t)nreq * K * 8, hipMemcpyDeviceToHost, slot.st);
-    (void)hipMemcpyAsync(slot.hflags, ar.flags, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, slot.st);
-    (void)hipEventRecord(slot.ev, slot.st);
+    const size_t out_bytes = (size_t)((char *)(ar.status + nreq) - (char *)ar.rows);
+    slot.failed = false;
+    slot.fail_msg.clear();
+    const char *step = "input copy";
+    hipError_t e = hipMemcpyAsync(ar.req_ptr, slot.hin, in_bytes, hipMemcpyHostToDevice, slot.st);
+    if (e == hipSuccess) {
+        FoldArgs a = fold_args(c, s->o.mode, ar, nreq, s->o.sweeps);
+        a.nchunks = (int32_t)nchunks;
+        step = "fold-in launch";
+        int32_t left = s->inject.load();
+        while (left > 0 && !s->inject.compare_exchange_weak(left, left - 1)) {}
+        e = left > 0 ? hipErrorLaunchFailure : launch_fold_compute(c->prec, a, total, s->o.method, slot.st);
+    }
+    if (e == hipSuccess) {
+        step = "row copy-back";
+        e = hipMemcpyAsync(slot.hout, ar.rows, out_bytes, hipMemcpyDeviceToHost, slot.st);
+    }
+    if (e == hipSuccess) {
+        step = "event record";
+        e = hipEventRecord(slot.ev, slot.st);
+    }
+    if (e != hipSuccess) {
+        slot.failed = true;
+        slot.fail_msg = std::string("serving batch: ") + step + " failed: " + hipGetErrorString(e);
+    }
 }
 
 void scheduler(tf_server *s)
@@ -280,16 +307,29 @@ void completer(tf_server *s, SSlot *slot)
         s->cv_slot.wait(lk, [&] { return s->stop || slot->launched; });
         if (!slot->launched) break;   // stop with nothing in flight
         lk.unlock();
-        (void)hipEventSynchronize(slot->ev);
+        // a failed batch: drain what was enqueued before the failure, so the
+        // slot's buffers are idle before the next batch, and read nothing back
+        const bool failed = slot->failed;
+        if (failed) (void)hipStreamSynchronize(slot->st);
+        else (void)hipEventSynchronize(slot->ev);
         const clk::time_point now = clk::now();
         const int K = s->ctx->K;
-        const bool failed = slot->hflags[1] != ULLONG_MAX;
+        const size_t nreq = slot->batch.size();
+        const double *rows = reinterpret_cast<const double *>(slot->hout);
+        const int32_t *status = reinterpret_cast<const int32_t *>(slot->hout + align256(nreq * (size_t)K * 8));
         lk.lock();
-        for (size_t q = 0; q < slot->batch.size(); ++q) {
+        if (failed) s->err = slot->fail_msg;
+        for (size_t q = 0; q < nreq; ++q) {
             SReq *r = slot->batch[q];
-            r->row.assign(slot->hout + q * K, slot->hout + (q + 1) * K);
+            if (failed) {
+                r->row.assign((size_t)K, std::nan(""));
+                r->status = TF_E_DEVICE;
+                s->failed += 1;
+            } else {
+                r->row.assign(rows + q * K, rows + (q + 1) * K);
+                r->status = status[q] == TF_OK ? TF_OK : TF_E_NUMERIC;
+            }
             r->t_done = now;
-            r->status = (failed && slot->hflags[1] == (unsigned long long)q) ? TF_E_NUMERIC : TF_OK;
             r->done = true;
             s->lat_us.push_back(std::chrono::duration<double, std::micro>(now - r->t_submit).count());
         }
@@ -310,7 +350,6 @@ void destroy_server(tf_server *s)
         if (sl->dev) ctx_free(s->ctx, sl->dev);
         if (sl->hin) (void)hipHostFree(sl->hin);
         if (sl->hout) (void)hipHostFree(sl->hout);
-        if (sl->hflags) (void)hipHostFree(sl->hflags);
     }
     delete s;
 }
@@ -367,9 +406,9 @@ tf_status tf_serve_open(tf_ctx *ctx, const tf_serve_opts *opts, tf_server **out)
         if (e == hipSuccess) e = ctx_alloc(ctx, &sl->dev, s->slot_bytes);
         if (e == hipSuccess) e = hipHostMalloc((void **)&sl->hin, s->slot_bytes, hipHostMallocDefault);
         if (e == hipSuccess)
-            e = hipHostMalloc((void **)&sl->hout, (size_t)o.max_batch * ctx->K * 8, hipHostMallocDefault);
-        if (e == hipSuccess)
-            e = hipHostMalloc((void **)&sl->hflags, 2 * sizeof(unsigned long long), hipHostMallocDefault);
+            e = hipHostMalloc((void **)&sl->hout,
+                              align256((size_t)o.max_batch * ctx->K * 8) + (size_t)o.max_batch * 4,
+                              hipHostMallocDefault);
         s->slots.push_back(std::move(sl));
         if (e != hipSuccess) {
             ctx->err = std::string("serving resources: ") + hipGetErrorString(e);
@@ -486,6 +525,7 @@ tf_status tf_serve_report(tf_server *s, tf_serve_stats *out)
     const double span = s->have_first ? std::chrono::duration<double>(s->t_last - s->t_first).count() : 0.0;
     out->solves_per_s = span > 0 ? (double)out->completed / span : 0.0;
     out->mean_batch = s->batches ? s->batch_sum / (double)s->batches : 0.0;
+    out->failed = s->failed;
     return TF_OK;
 }
 
@@ -499,6 +539,23 @@ tf_status tf_serve_reset_stats(tf_server *s)
     s->busy_rejects = 0;
     s->max_queue = 0;
     s->batch_sum = 0.0;
+    s->failed = 0;
+    return TF_OK;
+}
+
+const char *tf_serve_last_error(tf_server *s)
+{
+    if (!s) return "";
+    std::lock_guard<std::mutex> lk(s->mu);
+    thread_local std::string copy;
+    copy = s->err;
+    return copy.c_str();
+}
+
+tf_status tf_serve_inject_fault(tf_server *s, int32_t nbatches)
+{
+    if (!s || nbatches < 0) return TF_E_INVALID;
+    s->inject.store(nbatches);
     return TF_OK;
 }
 

@@ -404,6 +404,8 @@ tf_status run_split(tf_ctx *c, const int32_t *cols, int ncols, int T_in)
             sa.lambda = c->lambda;
             sa.reg_mode = c->opt.reg_mode;
             sa.bad = c->d_bad + n;
+            sa.flags = c->d_bad;
+            sa.nmodes = c->N;
             HIPCHK(c, launch_solve(c->prec, CP, sa, c->stream));
         }
     }
@@ -419,6 +421,7 @@ tf_status run_split(tf_ctx *c, const int32_t *cols, int ncols, int T_in)
 tf_status reset_bad(tf_ctx *c)
 {
     HIPCHK(c, hipMemsetAsync(c->d_bad, 0xff, kMaxModes * sizeof(unsigned long long), c->stream));
+    HIPCHK(c, hipMemsetAsync(c->d_bad + kStopWord, 0, 2 * sizeof(unsigned long long), c->stream));
     return TF_OK;
 }
 
@@ -430,7 +433,8 @@ tf_status check_bad(tf_ctx *c)
     for (int n = 0; n < c->N; ++n)
         if (h[n] != ULLONG_MAX)
             return CTX_FAIL(c, TF_E_NUMERIC,
-                            "non-positive Cholesky pivot in mode %d row %llu (row kept its previous value)",
+                            "non-positive Cholesky pivot in mode %d row %llu (row kept its previous value; "
+                            "no factor was updated after that mode pass)",
                             n, (unsigned long long)h[n]);
     return TF_OK;
 }
@@ -560,7 +564,7 @@ tf_status build_state(tf_ctx *c, const int32_t *d_idx, const double *d_vals)
     HIPCHK(c, dalloc(c, &c->x, (size_t)nnz));
     HIPCHK(c, hipMemcpyAsync(c->idx, d_idx, (size_t)nnz * N * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
     HIPCHK(c, hipMemcpyAsync(c->x, d_vals, (size_t)nnz * sizeof(double), hipMemcpyDeviceToDevice, st));
-    HIPCHK(c, dalloc(c, &c->d_bad, kMaxModes));
+    HIPCHK(c, dalloc(c, &c->d_bad, kFlagWords));
     HIPCHK(c, dalloc(c, &c->d_scalar, 4));
     HIPCHK(c, dalloc(c, &c->d_cols, 2 * (size_t)c->K + 2));
 
@@ -852,6 +856,7 @@ tf_status time_pass(tf_ctx *c, int n, int CP, int npend, bool first, void *rhat,
     SolveArgs sa;
     sa.rowptr = md.rowptr; sa.I = md.I; sa.gram = c->gram; sa.W = md.Z; sa.ld = c->ld;
     sa.lambda = c->lambda; sa.reg_mode = c->opt.reg_mode; sa.bad = c->d_bad + n;
+    sa.flags = c->d_bad; sa.nmodes = c->N;
     HIPCHK(c, launch_solve(c->prec, CP, sa, c->stream));
     HIPCHK(c, hipEventRecord(e1, c->stream));
     HIPCHK(c, hipEventSynchronize(e1));

@@ -25,6 +25,10 @@ struct bf16 {
 // precisions), 32 for the wide kernels (FP32 and BF16 storage).
 constexpr int kMaxC = 32;
 constexpr int kMaxModes = 8;
+// Words of the failure flags after the per-mode failing rows (see pass_latch).
+constexpr int kStopWord = kMaxModes;
+constexpr int kCountWord = kMaxModes + 1;
+constexpr int kFlagWords = kMaxModes + 2;
 
 // Gram record of one row: upper triangle of B (c1 <= c2, row-major) then the
 // right-hand side c; padded to a multiple of 4 entries.
@@ -67,6 +71,8 @@ struct SolveArgs {
     double lambda;
     int32_t reg_mode;
     unsigned long long *bad;   // smallest failing row (init ULLONG_MAX)
+    unsigned long long *flags; // failure flags of the sweep (bad == flags + mode)
+    int32_t nmodes;
 };
 
 // launchers (return hipError_t of the launch)
@@ -192,7 +198,7 @@ struct tf_ctx {
     void *gram = nullptr;     // max_I x gram_stride(slab_cp) (TA)
     void *gpart = nullptr;    // max_chunks x gram_stride(slab_cp) (TA)
     int32_t *d_cols = nullptr;  // device copy of split columns + pending columns
-    unsigned long long *d_bad = nullptr;  // [0] failing row, [1] scratch
+    unsigned long long *d_bad = nullptr;  // kFlagWords failure flags (pass_latch)
     double *d_partials = nullptr;
     int64_t partials_cap = 0;
     double *d_scalar = nullptr;

@@ -73,7 +73,8 @@ class tf_serve_stats(ctypes.Structure):
                 ("p50_us", ctypes.c_double), ("p90_us", ctypes.c_double),
                 ("p99_us", ctypes.c_double), ("p999_us", ctypes.c_double),
                 ("max_us", ctypes.c_double), ("mean_us", ctypes.c_double),
-                ("solves_per_s", ctypes.c_double), ("mean_batch", ctypes.c_double)]
+                ("solves_per_s", ctypes.c_double), ("mean_batch", ctypes.c_double),
+                ("failed", ctypes.c_int64)]
 
 
 TF_FOLDIN_FULL, TF_FOLDIN_CDTF = 0, 1
@@ -137,6 +138,9 @@ def lib():
         L.tf_serve_reset_stats.argtypes = [P]
         L.tf_serve_close.argtypes = [P]
         L.tf_serve_close.restype = None
+        L.tf_serve_last_error.argtypes = [P]
+        L.tf_serve_last_error.restype = ctypes.c_char_p
+        L.tf_serve_inject_fault.argtypes = [P, ctypes.c_int32]
         for name in ("tf_init", "tf_sweep", "tf_split", "tf_set_col_order", "tf_get_col_order",
                      "tf_loss", "tf_predict", "tf_get_factor", "tf_get_factor_block", "tf_set_factor",
                      "tf_resync",
@@ -340,6 +344,22 @@ def tf_serve_wait(srv, ticket, K):
     if rc != TF_OK:
         raise TFError(rc, "tf_serve_wait")
     return row, st
+
+
+def tf_serve_wait_status(srv, ticket, K):
+    """tf_serve_wait without raising: (status, row, stats)."""
+    row = np.empty(int(K), dtype=np.float64)
+    st = tf_req_stats()
+    rc = lib().tf_serve_wait(srv, ctypes.c_uint64(ticket), _np(row), ctypes.byref(st))
+    return int(rc), row, st
+
+
+def tf_serve_last_error(srv) -> str:
+    return lib().tf_serve_last_error(srv).decode()
+
+
+def tf_serve_inject_fault(srv, nbatches):
+    _check(None, lib().tf_serve_inject_fault(srv, int(nbatches)))
 
 
 def tf_serve_replay(srv, arrival_s, reqs):

@@ -114,12 +114,14 @@ def _serve_setup(prec="f32", K=24):
 def _slot_bytes_full_rank(N, K, ta, nreq, total):
     """Device bytes of a full-rank serving batch, as the library lays out its
     slot arena: request offsets, chunk tables, indices, values, P, partial
-    Gram records (one per 256-entry chunk), rows, flags; 256-byte aligned."""
+    Gram records (one per 256-entry chunk), rows, per-request status words,
+    flags; 256-byte aligned."""
     a = lambda b: (b + 255) & ~255
     nc = nreq + total // 256
     gs = (K * (K + 1) // 2 + K + 3) & ~3
     return (a((nreq + 1) * 8) + a((nreq + 1) * 4) + a(nc * 4) + a(total * (N - 1) * 4) +
-            a(total * 8) + a(total * K * ta) + a(nc * gs * ta) + a(nreq * K * 8) + 256)
+            a(total * 8) + a(total * K * ta) + a(nc * gs * ta) + a(nreq * K * 8) + a(nreq * 4) +
+            256)
 
 
 def _submit_all(tf, srv, ptr, oidx, vals, order):
@@ -166,6 +168,93 @@ def test_serving_alone_and_mixed_are_bit_identical(method):
         want = o.foldin_full(0, oidx[sl], vals[sl]) if method == 0 else \
             o.foldin_cdtf(0, oidx[sl], vals[sl], 3)
         assert rel_max(alone[q], want) < 1e-4
+    g.close()
+
+
+def test_serving_device_failures_are_reported_per_request():
+    """A batch whose launch fails (forced from the host through the
+    tf_serve_inject_fault hook: no kernel runs) completes every one of its
+    requests with TF_E_DEVICE and a NaN row, never TF_OK; the server keeps
+    serving, and later requests get the rows tf_foldin gives."""
+    from paper_1410_5209_amd import tf
+    note("serving injected launch failures")
+    g, o, ptr, oidx, vals = _serve_setup()
+    nreq = len(ptr) - 1
+    want = _gpu_foldin(g, 0, ptr, oidx, vals, 0)
+    srv = tf.tf_serve_open(g.ctx, tf.tf_serve_default_options(streams=2))
+    tf.tf_serve_inject_fault(srv, 3)
+    keep = []
+    for q in range(nreq):                      # one at a time: one request per batch
+        sl = slice(ptr[q], ptr[q + 1])
+        oi, va = np.ascontiguousarray(oidx[sl]), np.ascontiguousarray(vals[sl])
+        keep.append((oi, va))
+        t = tf.tf_serve_submit(srv, tf.make_request(oi, va))
+        rc, row, st = tf.tf_serve_wait_status(srv, t, g.K)
+        if q < 3:
+            assert rc == tf.TF_E_DEVICE and st.status == tf.TF_E_DEVICE
+            assert np.all(np.isnan(row))
+        else:
+            assert rc == tf.TF_OK and st.status == tf.TF_OK
+            assert np.array_equal(row, want[q])
+    assert "fold-in launch" in tf.tf_serve_last_error(srv)
+    rep = tf.tf_serve_report(srv)
+    assert rep.failed == 3 and rep.completed == nreq
+    # a failed batch in a burst: its requests fail together, the others do not
+    tf.tf_serve_inject_fault(srv, 1)
+    keep2, tickets = _submit_all(tf, srv, ptr, oidx, vals, list(range(nreq)))
+    nfail = 0
+    for q in range(nreq):
+        rc, row, st = tf.tf_serve_wait_status(srv, tickets[q], g.K)
+        if rc == tf.TF_E_DEVICE:
+            nfail += 1
+            assert np.all(np.isnan(row))
+        else:
+            assert rc == tf.TF_OK and np.array_equal(row, want[q])
+    assert 1 <= nfail < nreq
+    tf.tf_serve_close(srv)
+    g.close()
+
+
+def test_serving_numeric_failure_is_per_request():
+    """A request whose Gram matrix overflows (it meets a factor row of 1e200,
+    so a Cholesky pivot is NaN) completes with TF_E_NUMERIC and a zero row,
+    alone and inside a batch; the other requests of its batch complete with
+    TF_OK and the same rows as alone (the status is the request's own, not
+    the batch's)."""
+    from paper_1410_5209_amd import tf
+    note("serving per-request numeric status")
+    dims, K = [400, 300, 200], 12
+    idx, x, A = problem(36, dims, 20000, K, first_zero=False)
+    A[1][5, :] = 1e200
+    g, o = pair(dims, idx, x, A, K, 1.0, "f64")
+    sizes = [30, 8, 50, 3, 40, 12, 25, 9]
+    ptr, oidx, vals = _requests(dims, 0, sizes, 12)
+    oidx = oidx.copy()
+    oidx[ptr[1], 0] = 5                          # requests 1 and 5 meet row 5 of mode 1
+    oidx[ptr[5] + 2, 0] = 5
+    oidx[np.setdiff1d(np.arange(len(vals)), [ptr[1], ptr[5] + 2]), 0] %= 5
+    srv = tf.tf_serve_open(g.ctx, tf.tf_serve_default_options(streams=2))
+    alone = []
+    for q in range(len(sizes)):
+        sl = slice(ptr[q], ptr[q + 1])
+        oi, va = np.ascontiguousarray(oidx[sl]), np.ascontiguousarray(vals[sl])
+        t = tf.tf_serve_submit(srv, tf.make_request(oi, va))
+        alone.append(tf.tf_serve_wait_status(srv, t, K))
+    for q, (rc, row, st) in enumerate(alone):
+        if q in (1, 5):
+            assert rc == tf.TF_E_NUMERIC and np.all(row == 0.0)
+        else:
+            assert rc == tf.TF_OK
+            sl = slice(ptr[q], ptr[q + 1])
+            assert rel_max(row, o.foldin_full(0, oidx[sl], vals[sl])) < 1e-10
+    keep, tickets = _submit_all(tf, srv, ptr, oidx, vals, list(range(len(sizes))))
+    sizes_seen = []
+    for q in range(len(sizes)):
+        rc, row, st = tf.tf_serve_wait_status(srv, tickets[q], K)
+        sizes_seen.append(st.batch_size)
+        assert rc == alone[q][0] and np.array_equal(row, alone[q][1])
+    assert max(sizes_seen) > 1
+    tf.tf_serve_close(srv)
     g.close()
 
 

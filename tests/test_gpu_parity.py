@@ -492,6 +492,49 @@ def test_non_positive_pivot_is_reported_and_recovered_f64():
     g.close()
 
 
+@pytest.mark.parametrize("share", ["own", "shared"])
+def test_pivot_failure_in_a_later_split_stops_the_sweep_as_the_oracle_f64(share):
+    """K = 8, C = 3: blocks (0,1,2), (3,4,5), (6,7).  Mode 1's row 3 holds 1e200
+    in columns 3..5 and A^(1) = 0, so the first block runs normally and the
+    second block's mode-0 rows that meet that row get an infinite Gram
+    matrix.  The oracle stops its sweep after that mode pass (those rows keep
+    their values, the pass's other rows are updated, nothing after it
+    changes); the library must leave the same factors and residual and name
+    the same mode and smallest row."""
+    import re
+    from oracle import oracle as orc
+    from paper_1410_5209_amd import tf
+    dims, K = [40, 30, 20], 8
+    note(f"pivot failure in split 2 ({share})")
+    mode = {"own": tf.TF_RESID_OWN, "shared": tf.TF_RESID_SHARED}[share]
+    idx, x, A = problem(322, dims, 3000, K, first_zero=True)
+    A[1][3, 3:6] = 1e200
+    g, o = pair(dims, idx, x, A, K, 0.3, "f64", resid_share=mode)
+    with pytest.raises(tf.TFError) as e:
+        g.sweep(3, 2)
+    assert e.value.status == tf.TF_E_NUMERIC
+    m = re.search(r"mode (\d+) row (\d+)", str(e.value))
+    with pytest.raises(orc.OracleError) as oe:
+        o.sweep(3, 2)
+    obad = int(re.search(r"bad_row=(\d+)", str(oe.value)).group(1))
+    touched = np.unique(idx[idx[:, 1] == 3, 0])
+    assert m and int(m.group(1)) == 0 and int(m.group(2)) == obad == touched.min()
+    for n in range(3):
+        G, O = g.factor(n), o.get_factor(n)
+        keep = np.ones(dims[n], bool)
+        if n == 1:
+            keep[3] = False
+            assert np.array_equal(G[3, 3:], O[3, 3:])          # untouched huge values
+            assert rel_max(G[3, :3], O[3, :3]) < 1e-10
+        assert rel_max(G[keep], O[keep]) < 1e-10, n
+        assert np.array_equal(G[:, 6:], A[n][:, 6:])           # third block never updated
+    G0 = g.factor(0)
+    assert np.array_equal(G0[touched][:, 3:6], A[0][touched][:, 3:6])
+    rg, ro = g.residual(), o.residual()
+    assert np.max(np.abs(rg - ro)) < 1e-9 * np.max(np.abs(x))
+    g.close()
+
+
 @pytest.mark.parametrize("precision,share", [("f32", "own"), ("f32", "shared"), ("bf16", "own")])
 def test_wide_split_with_each_residual_placement(precision, share):
     """C = 32 with every mode keeping its own R-hat (each mode's first pass reads
