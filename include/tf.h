@@ -374,6 +374,20 @@ tf_status tf_profile(tf_ctx *ctx, int32_t enable);        /* 1 on, 0 off; resets
 tf_status tf_profile_read(tf_ctx *ctx, tf_kstats *out);    /* synchronises */
 
 /* ------------------------------------------------------------------ */
+/* Measurement probe (not part of the method): the rate of random 128-byte
+ * row gathers, the requests the row passes of a split are bound by.
+ *   d_table  device, rows x 32 floats (128-byte rows)
+ *   waves    wavefronts launched, a multiple of 4 (>= 4); each half
+ *            wavefront reads `steps` rows (a multiple of 8), chosen by a
+ *            SplitMix64-style hash of (seed, wave, step, half)
+ *   d_out    device, waves x 64 floats (one running sum per lane)
+ *   ms       out: HIP-event time of the launch on `stream`
+ * Gathers made: waves * 2 * steps rows.  Synchronises the stream.
+ * TF_E_INVALID for a count outside these rules. */
+tf_status tf_probe_gather(const void *d_table, int64_t rows, int64_t waves, int64_t steps,
+                          uint64_t seed, float *d_out, void *stream, double *ms);
+
+/* ------------------------------------------------------------------ */
 /* Host-only row planner (no GPU needed): classifies the rows of one mode
  * from its CSR offsets, as tf_init does for every mode.
  *   rowptr host[I + 1]; strategy, lane_nnz, split_threshold, chunk_nnz as in

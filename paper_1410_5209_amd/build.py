@@ -12,7 +12,7 @@ OUT = os.path.join(HERE, "libtfsals.so")
 OBJ = os.path.join(HERE, "_build")
 
 SOURCES = ["k_rows_f64.hip", "k_rows_f32.hip", "k_rows_bf16.hip", "k_build.hip", "k_slab.hip",
-           "k_eval.hip", "k_foldin.hip", "serve.hip", "plan.cpp", "tf_api.hip"]
+           "k_eval.hip", "k_foldin.hip", "k_big.hip", "k_probe.hip", "serve.hip", "plan.cpp", "tf_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -155,8 +155,25 @@ tf_status ensure_gram(tf_ctx *c, int CP)
     const size_t rec = (size_t)gram_stride(cp) * ta_size(c->prec);
     HIPCHK(c, ctx_alloc(c, &c->gram, (size_t)maxI * rec));
     HIPCHK(c, ctx_alloc(c, &c->gpart, (size_t)maxch * rec));
+    c->gpart_bytes = (size_t)maxch * rec;
     c->slab_cp = cp;
     c->gpart_chunks = maxch;
+    return TF_OK;
+}
+
+// Chunk records of the workgroup-per-row path for C columns.
+tf_status ensure_gpart_big(tf_ctx *c, int C)
+{
+    int64_t maxch = 1;
+    for (int n = 0; n < c->N; ++n) maxch = std::max<int64_t>(maxch, c->m[n].nchunks);
+    const size_t need = (size_t)maxch * (size_t)big_record_stride(C) * ta_size(c->prec);
+    if (c->gpart && c->gpart_bytes >= need) return TF_OK;
+    dfree(c, c->gpart);
+    c->gpart = nullptr;
+    c->gpart_bytes = 0;
+    c->gpart_chunks = 0;   // the narrow path re-sizes it for its records
+    HIPCHK(c, ctx_alloc(c, &c->gpart, need));
+    c->gpart_bytes = need;
     return TF_OK;
 }
 
@@ -341,20 +358,125 @@ tf_status place_residuals(tf_ctx *c, int CP, int npend, int T_in)
     return TF_OK;
 }
 
+// Mode 0's residual copy brought to R-hat of the columns `add` with the
+// pending columns' eq. (SALS_R) applied (k_big_boundary, from the factors,
+// which hold the pending columns' final values).  The other modes' own
+// copies no longer match it: they take it again through pos0 when next
+// used.  Clears the pending list.
+tf_status boundary_on_mode0(tf_ctx *c, const int32_t *d_add, int nadd)
+{
+    BoundaryArgs b;
+    std::memset(&b, 0, sizeof b);
+    b.r = c->m[0].rhat;
+    b.perm = c->m[0].perm;
+    b.idx = c->idx;
+    for (int n = 0; n < c->N; ++n) b.A[n] = c->m[n].A;
+    b.N = c->N;
+    b.K = c->K;
+    b.nnz = c->nnz;
+    b.add = d_add;
+    b.nadd = nadd;
+    b.sub = c->d_cols + c->K;
+    b.nsub = (int)c->pend.size();
+    HIPCHK(c, launch_big_boundary(c->prec, b, c->stream));
+    for (int n = 1; n < c->N; ++n) c->m[n].fresh = false;
+    c->pend.clear();
+    return TF_OK;
+}
+
+// Take the pending columns out of the residual before a pass that cannot
+// carry them (too many for its slab segments).
+tf_status flush_pending(tf_ctx *c)
+{
+    if (c->pend.empty()) return TF_OK;
+    tf_status s = upload_cols(c, nullptr, 0);
+    if (s != TF_OK) return s;
+    return boundary_on_mode0(c, c->d_cols, 0);
+}
+
+// A split wider than the narrow kernels take (k_big.hip): R-hat formed on
+// mode 0's copy, every mode reading that copy, factor rows updated in place.
+tf_status run_split_big(tf_ctx *c, const int32_t *cols, int ncols, int T_in)
+{
+    tf_status s = ensure_gpart_big(c, ncols);
+    if (s != TF_OK) return s;
+    if ((s = upload_cols(c, cols, ncols)) != TF_OK) return s;
+    if ((s = boundary_on_mode0(c, c->d_cols, ncols)) != TF_OK) return s;
+    for (int n = 1; n < c->N; ++n) {
+        if ((s = ensure_pos0(c, n)) != TF_OK) return s;
+        c->m[n].shared = true;
+    }
+    for (int it = 0; it < T_in; ++it) {
+        for (int n = 0; n < c->N; ++n) {
+            auto &md = c->m[n];
+            BigArgs a;
+            std::memset(&a, 0, sizeof a);
+            a.rowptr = md.rowptr;
+            a.items = md.items;
+            a.nitems = md.nitems;
+            a.split_rows = md.split_rows;
+            a.split_chunk_ptr = md.split_chunk_ptr;
+            a.nsplit = md.nsplit;
+            a.empty = md.empty;
+            a.nempty = md.nempty;
+            a.chunks = md.chunks;
+            a.nchunks = md.nchunks;
+            int t = 0;
+            for (int l = 0; l < c->N; ++l) {
+                if (l == n) continue;
+                a.oidx[t] = md.oidx[t];
+                a.A[t] = c->m[l].A;
+                ++t;
+            }
+            a.rhat = c->m[0].rhat;
+            a.rperm = n > 0 ? md.pos0 : nullptr;
+            a.Aown = md.A;
+            a.K = c->K;
+            a.cols = c->d_cols;
+            a.C = ncols;
+            a.no = c->N - 1;
+            a.gpart = c->gpart;
+            a.lambda = c->lambda;
+            a.reg_mode = c->opt.reg_mode;
+            a.bad = c->d_bad + n;
+            a.flags = c->d_bad;
+            a.nmodes = c->N;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (c->profiling) {
+                e0 = take_event(c);
+                e1 = take_event(c);
+                if (e0) HIPCHK(c, hipEventRecord(e0, c->stream));
+            }
+            HIPCHK(c, launch_big_pass(c->prec, a, c->stream));
+            if (c->profiling && e0 && e1) {
+                HIPCHK(c, hipEventRecord(e1, c->stream));
+                c->ev_pending.push_back(tf_ctx::Timed{e0, e1, alg_bytes(c, n, ncols, 0, false), false});
+            }
+        }
+    }
+    c->pend.assign(cols, cols + ncols);
+    return TF_OK;
+}
+
 // One split of Algorithm 1 on columns cols[0..ncols).
 tf_status run_split(tf_ctx *c, const int32_t *cols, int ncols, int T_in)
 {
+    if (pick_cp(ncols, c->prec) < 0) return run_split_big(c, cols, ncols, T_in);
+    // pending columns too many for this split's slab segments (after a wider
+    // split) are taken out of the residual first
+    if (pick_cp(std::max<int>(ncols, (int)c->pend.size()), c->prec) < 0) {
+        tf_status s0 = flush_pending(c);
+        if (s0 != TF_OK) return s0;
+    }
     // the kernels run at a width covering both this split's and the pending
     // columns, so the residual update stays fused into the first pass (the
     // padded columns are zero in every slab segment, which leaves the real
     // columns' solution unchanged and the padded ones at zero)
     int CP = pick_cp(std::max<int>(ncols, (int)c->pend.size()), c->prec);
-    if (CP < 0) CP = pick_cp(ncols, c->prec);
-    if (CP < 0) return CTX_FAIL(c, TF_E_UNSUPPORTED, "C = %d exceeds %d columns per split", ncols, kMaxC);
+    if (CP < 0) return CTX_FAIL(c, TF_E_UNSUPPORTED, "no kernel width for C = %d", ncols);
     tf_status s = ensure_gram(c, CP);
     if (s != TF_OK) return s;
     const int npend = (int)c->pend.size();
-    if (npend > CP) return CTX_FAIL(c, TF_E_UNSUPPORTED, "pending columns exceed the kernel width");
     if ((s = slab_geometry(c, std::max(CP, npend))) != TF_OK) return s;
     if ((s = upload_cols(c, cols, ncols)) != TF_OK) return s;
     const int32_t *d_cur = c->d_cols;
@@ -458,7 +580,12 @@ tf_status ensure_partials(tf_ctx *c, int64_t n)
 // Sum of r^2 over all entries (and optionally r in input order).
 tf_status eval_residual(tf_ctx *c, double *d_rout, double *se_out)
 {
-    // the pending columns go into the W segment of the slabs
+    // the pending columns go into the W segment of the slabs; more than a
+    // slab row holds (after a wide split) are taken out of the residual first
+    if (pick_cp((int)c->pend.size(), c->prec) < 0) {
+        tf_status s0 = flush_pending(c);
+        if (s0 != TF_OK) return s0;
+    }
     const int npend = (int)c->pend.size();
     tf_status s = slab_geometry(c, std::max(npend, 1));
     if (s != TF_OK) return s;
@@ -510,7 +637,7 @@ void destroy_ctx(tf_ctx *c)
         dfree(c, md.rhat); dfree(c, md.A); dfree(c, md.Z);
         dfree(c, md.tasks); dfree(c, md.items); dfree(c, md.chunks);
         dfree(c, md.split_rows); dfree(c, md.split_chunk_ptr);
-        dfree(c, md.pos0);
+        dfree(c, md.pos0); dfree(c, md.empty);
     }
     dfree(c, c->gram); dfree(c, c->gpart); dfree(c, c->d_cols); dfree(c, c->d_bad);
     dfree(c, c->d_partials); dfree(c, c->d_scalar);
@@ -538,14 +665,18 @@ tf_status apply_plan(tf_ctx *c, int n, int lane_nnz, int split_threshold, int ch
     plan_rows(md.h_rowptr.data(), md.I, strategy, lane_nnz, split_threshold, chunk_nnz, &plan);
     HIPCHK(c, hipStreamSynchronize(c->stream));
     dfree(c, md.tasks); dfree(c, md.items); dfree(c, md.chunks); dfree(c, md.split_rows); dfree(c, md.split_chunk_ptr);
+    dfree(c, md.empty);
     md.tasks = nullptr; md.items = nullptr; md.chunks = nullptr;
-    md.split_rows = nullptr; md.split_chunk_ptr = nullptr;
+    md.split_rows = nullptr; md.split_chunk_ptr = nullptr; md.empty = nullptr;
     tf_status s;
     if ((s = upload_vec(c, &md.tasks, plan.tasks)) != TF_OK) return s;
     if ((s = upload_vec(c, &md.items, plan.items)) != TF_OK) return s;
     if ((s = upload_vec(c, &md.chunks, plan.chunks)) != TF_OK) return s;
     if ((s = upload_vec(c, &md.split_rows, plan.split_rows)) != TF_OK) return s;
     if ((s = upload_vec(c, &md.split_chunk_ptr, plan.split_chunk_ptr)) != TF_OK) return s;
+    if ((s = upload_vec(c, &md.empty, plan.empty)) != TF_OK) return s;
+    md.nitems = (int32_t)plan.items.size();
+    md.nempty = (int32_t)plan.empty.size();
     md.ntasks = (int32_t)plan.tasks.size();
     md.nchunks = (int32_t)plan.chunks.size();
     md.nsplit = (int32_t)plan.split_rows.size();
@@ -800,7 +931,7 @@ tf_status tf_split(tf_ctx *ctx, int32_t ncols, const int32_t *h_cols, int32_t T_
         for (int p = 0; p < q; ++p)
             if (h_cols[p] == h_cols[q]) return CTX_FAIL(ctx, TF_E_INVALID, "column %d repeated", h_cols[q]);
     }
-    if (ncols > kMaxC) return CTX_FAIL(ctx, TF_E_UNSUPPORTED, "C = %d exceeds %d", ncols, kMaxC);
+    if (ncols > kMaxBigC) return CTX_FAIL(ctx, TF_E_UNSUPPORTED, "C = %d exceeds %d", ncols, kMaxBigC);
     tf_status s = check_ready(ctx);
     if (s != TF_OK) return s;
     if ((s = auto_tiles(ctx, ncols, T_in)) != TF_OK) return s;
@@ -817,7 +948,7 @@ tf_status tf_sweep(tf_ctx *ctx, int32_t C, int32_t T_in)
         C = ctx->tuned_C;
     }
     if (C < 1 || C > ctx->K || T_in < 1) return CTX_FAIL(ctx, TF_E_INVALID, "need 1 <= C <= K, T_in >= 1");
-    if (C > kMaxC) return CTX_FAIL(ctx, TF_E_UNSUPPORTED, "C = %d exceeds %d", C, kMaxC);
+    if (C > kMaxBigC) return CTX_FAIL(ctx, TF_E_UNSUPPORTED, "C = %d exceeds %d", C, kMaxBigC);
     tf_status s = check_ready(ctx);
     if (s != TF_OK) return s;
     if ((s = auto_tiles(ctx, C, T_in)) != TF_OK) return s;

@@ -75,6 +75,52 @@ struct SolveArgs {
     int32_t nmodes;
 };
 
+// Workgroup-per-row path for splits wider than the register and wide kernels
+// take (k_big.hip), up to kMaxBigC columns.
+constexpr int kMaxBigC = 128;
+struct BigArgs {
+    const int32_t *rowptr;               // this mode
+    const int32_t *items;                // non-empty rows that are not chunked
+    int32_t nitems;
+    const int32_t *split_rows;           // chunked rows, and their chunk ranges
+    const int32_t *split_chunk_ptr;
+    int32_t nsplit;
+    const int32_t *empty;                // rows with no entries
+    int32_t nempty;
+    const Chunk *chunks;
+    int32_t nchunks;
+    const int32_t *oidx[kMaxModes - 1];  // other modes ascending, CSR order
+    const void *rhat;                    // mode 0's residual copy (R-hat of the split)
+    const int32_t *rperm;                // non-null: entry q reads rhat[rperm[q]]
+    const void *A[kMaxModes - 1];        // other modes' factors (storage type)
+    void *Aown;                          // this mode's factor
+    int32_t K;
+    const int32_t *cols;                 // the split's columns (device, C)
+    int32_t C;
+    int32_t no;                          // N - 1
+    void *gpart;                         // chunk records, big_record_stride(C) each
+    double lambda;
+    int32_t reg_mode;
+    unsigned long long *bad;
+    unsigned long long *flags;
+    int32_t nmodes;
+};
+struct BoundaryArgs {
+    void *r;                             // mode 0's residual copy (CSR order)
+    const int32_t *perm;                 // mode 0's CSR order: entry of each position
+    const int32_t *idx;                  // input-order index tuples (nnz x N)
+    const void *A[kMaxModes];
+    int32_t N, K;
+    int64_t nnz;
+    const int32_t *add;                  // columns added back (R-hat of the split)
+    int32_t nadd;
+    const int32_t *sub;                  // pending columns taken out (eq. (SALS_R))
+    int32_t nsub;
+};
+hipError_t launch_big_pass(int prec, const BigArgs &a, hipStream_t st);
+hipError_t launch_big_boundary(int prec, const BoundaryArgs &a, hipStream_t st);
+int64_t big_record_stride(int C);
+
 // launchers (return hipError_t of the launch)
 hipError_t launch_accum(int prec, int CP, int no, bool first, const AccumArgs &a, int grid,
                         hipStream_t st);
@@ -175,6 +221,9 @@ struct tf_ctx {
         tfk::Task *tasks = nullptr;
         int32_t ntasks = 0;
         int32_t *items = nullptr;
+        int32_t nitems = 0;
+        int32_t *empty = nullptr;           // rows with no entries
+        int32_t nempty = 0;
         tfk::Chunk *chunks = nullptr;
         int32_t nchunks = 0;
         int32_t *split_rows = nullptr;
@@ -197,6 +246,7 @@ struct tf_ctx {
     int tuned_C = 0;          // chosen by tf_autotune (0: none)
     void *gram = nullptr;     // max_I x gram_stride(slab_cp) (TA)
     void *gpart = nullptr;    // max_chunks x gram_stride(slab_cp) (TA)
+    size_t gpart_bytes = 0;   // its size
     int32_t *d_cols = nullptr;  // device copy of split columns + pending columns
     unsigned long long *d_bad = nullptr;  // kFlagWords failure flags (pass_latch)
     double *d_partials = nullptr;

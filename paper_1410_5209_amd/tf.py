@@ -141,6 +141,8 @@ def lib():
         L.tf_serve_last_error.argtypes = [P]
         L.tf_serve_last_error.restype = ctypes.c_char_p
         L.tf_serve_inject_fault.argtypes = [P, ctypes.c_int32]
+        L.tf_probe_gather.argtypes = [P, i64, i64, i64, ctypes.c_uint64, P, P,
+                                      ctypes.POINTER(ctypes.c_double)]
         for name in ("tf_init", "tf_sweep", "tf_split", "tf_set_col_order", "tf_get_col_order",
                      "tf_loss", "tf_predict", "tf_get_factor", "tf_get_factor_block", "tf_set_factor",
                      "tf_resync",
@@ -352,6 +354,15 @@ def tf_serve_wait_status(srv, ticket, K):
     st = tf_req_stats()
     rc = lib().tf_serve_wait(srv, ctypes.c_uint64(ticket), _np(row), ctypes.byref(st))
     return int(rc), row, st
+
+
+def tf_probe_gather(d_table, rows, waves, steps, seed, d_out, stream=None) -> float:
+    """Milliseconds of one random-row gather launch (see include/tf.h)."""
+    ms = ctypes.c_double()
+    _check(None, lib().tf_probe_gather(_dev(d_table), int(rows), int(waves), int(steps),
+                                       ctypes.c_uint64(seed), _dev(d_out), stream,
+                                       ctypes.byref(ms)))
+    return ms.value
 
 
 def tf_serve_last_error(srv) -> str:

@@ -12,7 +12,9 @@ at any size, since the oracle cannot follow 1e8-entry tensors.
   sum_{j in Omega_i} r_j p_j = lambda a_i, with r the maintained residual and
   p_j the elementwise product of the other modes' split columns at entry j.
   Checked on sampled rows of the last mode, long rows (several workgroups per
-  row) among them, to 1e-4 of the summed magnitudes of the terms: FP32 storage
+  row, and on the 5-way tensor rows of up to 2e6 entries and one whose chunks
+  are lengthened to keep 1024 per row) among them, to 1e-4 of the summed
+  magnitudes of the terms: FP32 storage
   and accumulation leave ~1e-6, a wrong, missing or misplaced term leaves O(1),
   a dropped lambda term O(1e-2) on the short rows.
 * Residual (R, Section 3.1): r_j = x_j - sum_k prod_n a^(n)_{i_n k} on sampled
@@ -82,34 +84,48 @@ def _gather_products(m, idx, J, skip, cols):
     return P
 
 
-def _check_split_optimality(m, idx, resid, rp, pm, rows, cols, lam, reg_mode, batch=300_000):
+def _pieces(rp, rows, batch):
+    """Windows of at most `batch` entries over the listed rows (a long row is
+    cut across windows): lists of (row slot, first position, end position)."""
+    win, tot = [], 0
+    for k, i in enumerate(rows):
+        b, e = int(rp[i]), int(rp[i + 1])
+        while b < e:
+            take = min(e - b, batch - tot)
+            win.append((k, b, b + take))
+            tot += take
+            b += take
+            if tot == batch:
+                yield win
+                win, tot = [], 0
+    if win:
+        yield win
+
+
+def _check_split_optimality(m, idx, resid, rp, pm, rows, cols, lam, reg_mode, batch=1_000_000):
+    """Worst relative gradient of eq. (SALS) over the listed rows of the last
+    mode, the sums over each row's entries taken in windows of `batch`
+    entries (so rows of tens of millions of entries fit host memory)."""
     n = m.N - 1
     lens = (rp[rows + 1] - rp[rows]).astype(np.int64)
     assert np.all(lens > 0)
-    worst, checked = 0.0, 0
-    q = 0
-    while q < rows.shape[0]:
-        e = q
-        tot = 0
-        while e < rows.shape[0] and (e == q or tot + lens[e] <= batch):
-            tot += lens[e]
-            e += 1
-        br, bl = rows[q:e], lens[q:e]
-        J = np.concatenate([pm[rp[i]:rp[i + 1]] for i in br]).astype(np.int64)
-        seg = np.repeat(np.arange(br.shape[0]), bl)
-        starts = np.concatenate([[0], np.cumsum(bl)[:-1]])
+    a = m.factor_block(n, rows, cols)
+    g = np.zeros_like(a)
+    sc = np.zeros_like(a)
+    for win in _pieces(rp, rows, batch):
+        J = np.concatenate([pm[b:e] for _, b, e in win]).astype(np.int64)
+        seg = np.repeat(np.array([k for k, _, _ in win]), [e - b for _, b, e in win])
+        starts = np.concatenate([[0], np.cumsum([e - b for _, b, e in win])[:-1]]).astype(np.int64)
+        slots = np.array([k for k, _, _ in win])
         P = _gather_products(m, idx, J, n, cols)
-        a = m.factor_block(n, br, cols)
         r = resid[J]
-        g = np.add.reduceat(r[:, None] * P, starts, axis=0)
         s = np.abs(r) + (np.abs(P) * np.abs(a[seg])).sum(axis=1)
-        lw = lam * (bl[:, None].astype(np.float64) if reg_mode == 1 else 1.0)
-        scale = np.add.reduceat(np.abs(P) * s[:, None], starts, axis=0) + lw * np.abs(a)
-        err = np.abs(g - lw * a) / np.maximum(scale, 1e-300)
-        worst = max(worst, float(err.max()))
-        checked += br.shape[0]
-        q = e
-    return worst, checked
+        np.add.at(g, slots, np.add.reduceat(r[:, None] * P, starts, axis=0))
+        np.add.at(sc, slots, np.add.reduceat(np.abs(P) * s[:, None], starts, axis=0))
+        del P
+    lw = lam * (lens[:, None].astype(np.float64) if reg_mode == 1 else 1.0)
+    err = np.abs(g - lw * a) / np.maximum(sc + lw * np.abs(a), 1e-300)
+    return float(err.max()), int(rows.shape[0])
 
 
 def _check_residual(m, idx, x, resid, rng, nsample):
@@ -148,11 +164,11 @@ def _check_foldin(m, w, F, nreq=200):
     return worst, int(np.max(np.diff(ptr)))
 
 
-def _model(w, idx, x, T_in, cands):
+def _model(w, idx, x, T_in, cands, with_tune=False):
     from paper_1410_5209_amd.model import SparseCP
     m = SparseCP(w.dims, idx, x, w.K, w.lam, precision=w.prec)
     r = m.autotune(T_in, cands, tune_tiles=True)
-    return m, int(r.best_C)
+    return (m, int(r.best_C), r) if with_tune else (m, int(r.best_C))
 
 
 @pytest.mark.timeout(900)
@@ -224,15 +240,23 @@ def test_fullsize_5way_zipf():
     note(f"fullsize {w.name}: generating {w.nnz} draws")
     idx, x = synth.make_tensor(w)
     note(f"fullsize {w.name}: init + autotune C in [16, 32]")
-    m, C = _model(w, idx, x, w.T_in, [16, 32])
+    m, C, tune = _model(w, idx, x, w.T_in, [16, 32], with_tune=True)
     last_mode = w.N - 1
     for n in (0, last_mode):
         note(f"fullsize {w.name}: CSR mode {n}")
         rp, pm = _check_csr(m, idx, n, w.dims[n])
     rng = np.random.default_rng(12)
     # short rows at random, 20 rows split across workgroups, the 3 longest
-    # rows of at most 2e5 entries (the longest rows hold ~3e7 entries)
-    rows = _rows_to_check(rp, rng, 2000, 20, (8192, 50_000), 200_000)
+    # rows of at most 2e6 entries, and the shortest row whose chunks are
+    # lengthened so that it has at most 1024 of them (the longest rows hold
+    # ~3e7 entries; their sums run the longest FP32 accumulation chains)
+    rows = _rows_to_check(rp, rng, 2000, 20, (8192, 50_000), 2_000_000)
+    lens = np.diff(rp)
+    over = np.flatnonzero(lens > 1024 * int(tune.chunk_nnz[last_mode]))
+    if over.size:
+        rows = np.unique(np.concatenate([rows, [over[np.argmin(lens[over])]]])).astype(np.int64)
+    note(f"fullsize {w.name}: checking rows of up to {int(lens[rows].max())} entries "
+         f"(chunk length {int(tune.chunk_nnz[last_mode])})")
     order = m.col_order()
     note(f"fullsize {w.name}: one sweep C={C} T_in={w.T_in}")
     m.sweep(C, w.T_in)

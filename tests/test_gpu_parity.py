@@ -370,17 +370,6 @@ def test_four_mode_short_tail_shape_wide_f32():
     g.close()
 
 
-def test_f64_rejects_wide_split():
-    from paper_1410_5209_amd import tf
-    dims, K = [20, 20, 20], 40
-    idx, x, A = problem(211, dims, 2000, K)
-    g, _ = pair(dims, idx, x, A, K, 0.5, "f64")
-    with pytest.raises(tf.TFError) as e:
-        g.split(list(range(20)), 1)
-    assert e.value.status == tf.TF_E_UNSUPPORTED
-    g.close()
-
-
 def test_autotune_leaves_model_unchanged_and_sweeps_with_chosen_width():
     dims, K = [400, 300, 200], 40
     note("autotune")
