@@ -22,9 +22,19 @@
 
 namespace tfk {
 
-template <int PREC, int CP, int NO, bool FIRST>
-__global__ __launch_bounds__(256) void k_accum(AccumArgs a)
+// FM: 0 a plain pass; 1 a split's first pass in which no other mode has
+// been updated yet (the split-start segments S equal W and are not read);
+// 2 a first pass that reads S for the modes already updated.
+// The FM = 1 first pass at C = 10 with two other modes (3-way tensors) is
+// asked for 3 waves per SIMD in FP32 / BF16: it fits 168 registers with 4
+// spilled, where left alone it takes 172 and runs 2 waves.  Other
+// instantiations are left to the compiler (forcing them spills up to
+// hundreds of registers).
+template <int PREC, int CP, int NO, int FM>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu((FM == 1 && CP == 10 && NO == 2 && PREC != P_F64) ? 3 : 1))) void k_accum(AccumArgs a)
 {
+    constexpr bool FIRST = FM > 0;
     using TS = typename Types<PREC>::TS;
     using TR = typename Types<PREC>::TR;
     using TA = typename Types<PREC>::TA;
@@ -155,7 +165,7 @@ __global__ __launch_bounds__(256) void k_accum(AccumArgs a)
                 load_row<CP>(row_l, w[l]);
                 if (a.has_pend)
                     load_row8<CP>(reinterpret_cast<const TS *>(a.P[l]) + (int64_t)ix[l] * ld, pv[l]);
-                if (a.before[l])
+                if (FM == 2 && a.before[l])
                     load_row<CP>(reinterpret_cast<const TS *>(a.S[l]) + (int64_t)ix[l] * ld, sv[l]);
             }
         };
@@ -190,7 +200,7 @@ __global__ __launch_bounds__(256) void k_accum(AccumArgs a)
 #pragma unroll
                     for (int c = 0; c < CP; ++c) tp[c] *= pv[l][c];
                 }
-                if (a.before[l]) {
+                if (FM == 2 && a.before[l]) {
 #pragma unroll
                     for (int c = 0; c < CP; ++c) ts[c] *= sv[l][c];
                 } else {
@@ -198,8 +208,14 @@ __global__ __launch_bounds__(256) void k_accum(AccumArgs a)
                     for (int c = 0; c < CP; ++c) ts[c] *= w[l][c];
                 }
             }
-            const TR rcur = rh;
-            const int64_t jcur = j;
+            // R-hat of this split from the previous split's residual state
+            // (summed before the next entry's segments are requested, so the
+            // products' registers are free for them)
+            TA dr = TA(0), ds = TA(0);
+#pragma unroll
+            for (int c = 0; c < CP; ++c) { dr += tp[c]; ds += ts[c]; }
+            const TA r = ((TA)rh - dr) + ds;
+            stream_store((TR)r, rhat + j);
             if (jn < end) {
                 rh = rn;
                 fetch(in_, w, pv, sv);
@@ -210,12 +226,6 @@ __global__ __launch_bounds__(256) void k_accum(AccumArgs a)
                     rn = stream_load(rhat + jnn);
                 }
             }
-            // R-hat of this split from the previous split's residual state
-            TA dr = TA(0), ds = TA(0);
-#pragma unroll
-            for (int c = 0; c < CP; ++c) { dr += tp[c]; ds += ts[c]; }
-            const TA r = ((TA)rcur - dr) + ds;
-            stream_store((TR)r, rhat + jcur);
 
             int e = 0;
 #pragma unroll
@@ -271,7 +281,7 @@ __global__ __launch_bounds__(256) void k_accum(AccumArgs a)
 #pragma unroll
                     for (int c = 0; c < CP; ++c) tp[c] *= v[c];
                 }
-                if (a.before[l]) {
+                if (FM == 2 && a.before[l]) {
                     TA v[CP];
                     load_row<CP>(reinterpret_cast<const TS *>(a.S[l]) + (int64_t)cur[l] * ld, v);
 #pragma unroll

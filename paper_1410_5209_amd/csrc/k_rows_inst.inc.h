@@ -10,10 +10,14 @@ namespace tfk {
 template <int PREC, int CP, int NO>
 static hipError_t accum_no(bool first, const AccumArgs &a, int grid, hipStream_t st)
 {
-    if (first)
-        hipLaunchKernelGGL((k_accum<PREC, CP, NO, true>), dim3(grid), dim3(256), 0, st, a);
+    bool any_before = false;
+    for (int l = 0; l < NO; ++l) any_before |= a.before[l] != 0;
+    if (first && any_before)
+        hipLaunchKernelGGL((k_accum<PREC, CP, NO, 2>), dim3(grid), dim3(256), 0, st, a);
+    else if (first)
+        hipLaunchKernelGGL((k_accum<PREC, CP, NO, 1>), dim3(grid), dim3(256), 0, st, a);
     else
-        hipLaunchKernelGGL((k_accum<PREC, CP, NO, false>), dim3(grid), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_accum<PREC, CP, NO, 0>), dim3(grid), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -4,14 +4,21 @@ Reads
   --stats DIR    output of `rocprofv3 --kernel-trace --stats --output-format csv`
   --fetch CSV    counter_collection.csv of a `--pmc FETCH_SIZE` run
   --write CSV    counter_collection.csv of a `--pmc WRITE_SIZE` run
+  --reads CSV    counter_collection.csv of a `--pmc TCC_EA0_RDREQ_32B_sum
+                 TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum` run
+  --writes CSV   counter_collection.csv of a `--pmc TCC_EA0_WRREQ_sum
+                 TCC_EA0_WRREQ_64B_sum TCC_HIT_sum TCC_MISS_sum` run
 and writes
-  profiles/<kernel>_<workload>.md          per-kernel durations + traffic
-  profiles/<kernel>_<workload>_traffic.json DRAM-side bytes per launch of the
-                                            row-accumulation kernel, tagged with
-                                            the hash of its source
-Counter runs include a plain 1 GiB device copy (bench.py --calibrate-copy);
-its FETCH_SIZE / WRITE_SIZE readings against 1 GiB give the scale factor
-applied to the kernel's readings.
+  profiles/k_accum_<workload>.md          per-kernel durations and traffic
+  profiles/k_accum_<workload>_traffic.json bytes per launch of the row-
+                                           accumulation kernels, tagged with
+                                           the hash of their source
+HBM-side bytes are the L2's requests to memory by size: read requests of 32,
+64 and 128 bytes, write requests of 32 and 64 bytes.  FETCH_SIZE and
+WRITE_SIZE (the counters' own byte formulas) are reported beside them, each
+scaled by what it reads for a plain 1 GiB device copy in the same run
+(bench.py --calibrate-copy).  Both are L2-miss traffic: requests the 256 MB
+last-level cache serves are counted too.
 """
 from __future__ import annotations
 
@@ -29,14 +36,20 @@ sys.path.insert(0, ROOT)
 COPY_BYTES = 1 << 30
 
 
-def _counter_rows(path):
+def _rows(path):
     with open(path) as f:
-        return list(csv.DictReader(f))
+        rows = list(csv.DictReader(f))
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    return rows
 
 
-def _per_kernel(rows, name_filter):
-    vals = [float(r["Counter_Value"]) for r in rows if name_filter(r["Kernel_Name"])]
-    return vals
+def _per_dispatch(path, want):
+    """{dispatch id: {counter: value}} for the dispatches whose kernel name passes `want`."""
+    per = {}
+    for r in _rows(path):
+        if want(r["Kernel_Name"]):
+            per.setdefault(int(r["Dispatch_Id"]), {})[r["Counter_Name"]] = float(r["Counter_Value"])
+    return per
 
 
 def _is_accum(name):
@@ -47,26 +60,21 @@ def _is_copy(name):
     return "copyBuffer" in name
 
 
-def counter_bytes(path, last=0):
-    """(kernel KiB per launch mean, copy KiB mean, launches) from one counter CSV;
-    with last > 0 only the last `last` accumulation launches (the timed sweeps,
-    after any tuning trials) are averaged."""
-    rows = _counter_rows(path)
-    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
-    acc = _per_kernel(rows, _is_accum)
-    if last > 0:
-        acc = acc[-last:]
-    # the calibration: bench.py --calibrate-copy runs three 1 GiB copies back
-    # to back, i.e. three consecutive copy dispatches with equal readings
-    cps = [(int(r["Dispatch_Id"]), float(r["Counter_Value"])) for r in rows if _is_copy(r["Kernel_Name"])]
-    cp = []
+def _last(per, n):
+    ids = sorted(per)
+    return [per[i] for i in (ids[-n:] if n > 0 else ids)]
+
+
+def _copy_reading(path, counter):
+    """The counter's reading for the calibration copy: three consecutive copy
+    dispatches with equal readings (bench.py --calibrate-copy)."""
+    cps = sorted((i, v.get(counter, 0.0)) for i, v in _per_dispatch(path, _is_copy).items())
     for q in range(len(cps) - 2):
         ids = [cps[q + t][0] for t in range(3)]
         vals = [cps[q + t][1] for t in range(3)]
         if ids == [ids[0], ids[0] + 1, ids[0] + 2] and min(vals) > 0 and max(vals) / min(vals) < 1.01:
-            cp = vals
-            break
-    return (statistics.mean(acc) if acc else None, statistics.mean(cp) if cp else None, len(acc))
+            return statistics.mean(vals)
+    return None
 
 
 def kernel_stats(stats_dir):
@@ -95,16 +103,17 @@ def timed_launches(stats_dir, n):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--stats", required=True)
-    ap.add_argument("--fetch")
-    ap.add_argument("--write")
     ap.add_argument("--workload", required=True)
     ap.add_argument("--stats-cmd", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
     ap.add_argument("--fetch-cmd", default="")
     ap.add_argument("--write-cmd", default="")
+    ap.add_argument("--reads")
+    ap.add_argument("--writes")
+    ap.add_argument("--reads-cmd", default="")
+    ap.add_argument("--writes-cmd", default="")
     ap.add_argument("--bench-json", default=None, help="bench.py output line of the same build")
-    ap.add_argument("--tcc", default=None,
-                    help="counter_collection.csv of a `--pmc TCC_HIT_sum TCC_MISS_sum` run")
-    ap.add_argument("--tcc-cmd", default="")
     ap.add_argument("--timed", type=int, default=0,
                     help="accumulation launches of the timed sweeps in the stats run")
     ap.add_argument("--last", type=int, default=0,
@@ -126,53 +135,76 @@ def main():
     acc = [r for r in stats if "k_accum" in r["Name"]]
     calls = sum(int(r["Calls"]) for r in acc)
     avg_us = sum(float(r["TotalDurationNs"]) for r in acc) / max(calls, 1) / 1e3
-    lines += ["", f"All accumulation launches (k_accum*): {calls} calls, average {avg_us:.1f} us per launch "
-              "(tuning trials included)."]
+    lines += ["", f"All accumulation launches (k_accum*): {calls} calls, average {avg_us:.1f} us per "
+              "launch (tuning trials included)."]
+    t_us = None
     if args.timed:
         t_us = timed_launches(args.stats, args.timed)
         if t_us is not None:
-            lines += ["", f"Timed sweeps of the same run (the last {args.timed} accumulation launches of "
-                      f"its kernel trace): average {t_us:.1f} us per launch."]
+            lines += ["", f"Timed sweeps of the same run (the last {args.timed} accumulation launches "
+                      f"of its kernel trace): average {t_us:.1f} us per launch."]
 
-    traffic = None
+    traffic = {"kernel_source_sha": kernel_source_hash(), "workload": args.workload}
+    if args.reads and args.writes:
+        rd = _last(_per_dispatch(args.reads, _is_accum), args.last)
+        wr = _last(_per_dispatch(args.writes, _is_accum), args.last)
+        rbytes = statistics.mean(d.get("TCC_EA0_RDREQ_32B_sum", 0) * 32 + d.get("TCC_EA0_RDREQ_64B_sum", 0) * 64
+                                 + d.get("TCC_EA0_RDREQ_128B_sum", 0) * 128 for d in rd)
+        wbytes = statistics.mean(d.get("TCC_EA0_WRREQ_64B_sum", 0) * 64 +
+                                 (d.get("TCC_EA0_WRREQ_sum", 0) - d.get("TCC_EA0_WRREQ_64B_sum", 0)) * 32
+                                 for d in wr)
+        hits = statistics.mean(d.get("TCC_HIT_sum", 0) for d in wr)
+        miss = statistics.mean(d.get("TCC_MISS_sum", 0) for d in wr)
+        r128 = statistics.mean(d.get("TCC_EA0_RDREQ_128B_sum", 0) for d in rd)
+        rall = statistics.mean(d.get("TCC_EA0_RDREQ_32B_sum", 0) + d.get("TCC_EA0_RDREQ_64B_sum", 0)
+                               + d.get("TCC_EA0_RDREQ_128B_sum", 0) for d in rd)
+        # the same counters for the calibration copy: 1 GiB each way
+        crd = _copy_reading(args.reads, "TCC_EA0_RDREQ_128B_sum")
+        traffic.update({"read_bytes_per_launch": rbytes, "write_bytes_per_launch": wbytes,
+                        "bytes_per_launch": rbytes + wbytes, "launches_sampled": len(rd),
+                        "l2_hits_per_launch": hits, "l2_misses_per_launch": miss,
+                        "hit_rate": hits / max(hits + miss, 1.0),
+                        "read_requests_128b_share": r128 / max(rall, 1.0),
+                        "copy_128b_read_requests": crd})
+        lines += ["", "## HBM-side traffic of the accumulation kernels (rocprofv3 --pmc)", "",
+                  "Bytes are the L2's read requests of 32, 64 and 128 bytes and write requests of "
+                  "32 and 64 bytes (TCC_EA0_*), i.e. lines that miss L2 (the 256 MB last-level "
+                  "cache's hits included).", "",
+                  f"Read-request command: `{args.reads_cmd}`", "",
+                  f"Write-request / hit-rate command: `{args.writes_cmd}`", "",
+                  f"Per accumulation launch (mean of the last {len(rd)} launches, the timed sweep): "
+                  f"read {rbytes/1e9:.3f} GB, write {wbytes/1e9:.3f} GB, total {(rbytes+wbytes)/1e9:.3f} GB; "
+                  f"{100 * r128 / max(rall, 1.0):.1f}% of read requests are whole 128-byte lines.",
+                  "", f"L2 (TCC): {hits:.4g} hits, {miss:.4g} misses per launch, hit rate "
+                  f"{100 * hits / max(hits + miss, 1):.1f}%."]
+        if crd:
+            lines += ["", f"Check: the 1 GiB calibration copy makes {crd:.4g} 128-byte read requests "
+                      f"({crd * 128 / COPY_BYTES:.3f} GiB)."]
+        if t_us:
+            lines += ["", f"At the timed launches' average ({t_us:.1f} us): "
+                      f"{(rbytes + wbytes) / 1e3 / t_us:.0f} GB/s of HBM-side traffic "
+                      f"({100 * (rbytes + wbytes) / 1e3 / t_us / 8000:.1f}% of 8 TB/s), "
+                      f"{miss / 1e3 / t_us:.1f} G L2-miss lines/s."]
     if args.fetch and args.write:
-        fk, fc, nf = counter_bytes(args.fetch, args.last)
-        wk, wc, nw = counter_bytes(args.write, args.last)
+        fk = statistics.mean(d["FETCH_SIZE"] for d in _last(_per_dispatch(args.fetch, _is_accum), args.last))
+        wk = statistics.mean(d["WRITE_SIZE"] for d in _last(_per_dispatch(args.write, _is_accum), args.last))
+        fc = _copy_reading(args.fetch, "FETCH_SIZE")
+        wc = _copy_reading(args.write, "WRITE_SIZE")
         ffac = (COPY_BYTES / 1024) / fc if fc else 1.0
         wfac = (COPY_BYTES / 1024) / wc if wc else 1.0
-        fbytes = fk * 1024 * ffac
-        wbytes = wk * 1024 * wfac
-        traffic = {"kernel_source_sha": kernel_source_hash(), "workload": args.workload,
-                   "fetch_bytes_per_launch": fbytes, "write_bytes_per_launch": wbytes,
-                   "bytes_per_launch": fbytes + wbytes, "launches_sampled": nf,
-                   "copy_fetch_kib": fc, "copy_write_kib": wc,
-                   "fetch_scale": ffac, "write_scale": wfac}
-        lines += ["", "## HBM-side traffic of the accumulation kernels (rocprofv3 --pmc)", "",
-                  f"FETCH_SIZE command: `{args.fetch_cmd}`", "",
-                  f"WRITE_SIZE command: `{args.write_cmd}`", "",
-                  "A 1 GiB device copy (`__amd_rocclr_copyBuffer`) in the same runs calibrates the "
-                  f"counters: FETCH_SIZE read {fc:.0f} KiB (scale {ffac:.4f}), WRITE_SIZE read "
-                  f"{wc:.0f} KiB (scale {wfac:.4f}) for 1048576 KiB moved.", "",
-                  f"per accumulation launch (mean of the last {nf} launches, the timed sweep): "
-                  f"fetch {fbytes/1e9:.3f} GB, "
-                  f"write {wbytes/1e9:.3f} GB, total {(fbytes+wbytes)/1e9:.3f} GB."]
-        tpath = os.path.join(ROOT, "profiles", f"k_accum_{args.workload}_traffic.json")
-        with open(tpath, "w") as f:
+        traffic.update({"fetch_size_bytes_per_launch": fk * 1024 * ffac + wk * 1024 * wfac,
+                        "fetch_scale": ffac, "write_scale": wfac})
+        lines += ["", "## FETCH_SIZE / WRITE_SIZE, calibrated", "",
+                  f"FETCH_SIZE command: `{args.fetch_cmd}`", "", f"WRITE_SIZE command: `{args.write_cmd}`",
+                  "", f"A 1 GiB device copy in the same runs reads FETCH_SIZE {fc} KiB (scale "
+                  f"{ffac:.4f}) and WRITE_SIZE {wc} KiB (scale {wfac:.4f}); per accumulation launch: "
+                  f"fetch {fk * 1024 * ffac / 1e9:.3f} GB, write {wk * 1024 * wfac / 1e9:.3f} GB "
+                  "(the fetch scale is taken from a streaming copy of whole lines; applied to a "
+                  "kernel whose reads are also whole 128-byte lines it agrees with the request count "
+                  "above)."]
+    if "bytes_per_launch" in traffic:
+        with open(os.path.join(ROOT, "profiles", f"k_accum_{args.workload}_traffic.json"), "w") as f:
             json.dump(traffic, f, indent=1)
-    if args.tcc:
-        rows = _counter_rows(args.tcc)
-        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
-        per = {}
-        for r in rows:
-            if _is_accum(r["Kernel_Name"]):
-                per.setdefault(int(r["Dispatch_Id"]), {})[r["Counter_Name"]] = float(r["Counter_Value"])
-        ids = sorted(per)[-args.last:] if args.last > 0 else sorted(per)
-        hit = sum(per[i].get("TCC_HIT_sum", 0.0) for i in ids)
-        miss = sum(per[i].get("TCC_MISS_sum", 0.0) for i in ids)
-        lines += ["", "## L2 (TCC) hit rate of the accumulation kernels", "",
-                  f"Command: `{args.tcc_cmd}`", "",
-                  f"last {len(ids)} launches (the timed sweep): {hit:.4g} hits, {miss:.4g} misses, "
-                  f"hit rate {100 * hit / max(hit + miss, 1):.1f}%."]
     if args.bench_json:
         with open(args.bench_json) as f:
             b = json.loads([l for l in f if l.startswith("{")][-1])
@@ -180,8 +212,8 @@ def main():
         lines += ["", "## bench.py line of the same build", "",
                   f"value {b['value']:.4g} {b['unit']}, {b['ms_per_step']:.1f} ms per sweep; "
                   f"accumulation kernels: average launch {rf['avg_launch_ms']:.3f} ms (HIP events), "
-                  f"{rf['alg_bytes_per_launch']/1e9:.3f} GB algorithmic per launch, "
-                  f"achieved {rf['achieved']:.0f} GB/s = {100*rf['frac']:.1f}% of 8 TB/s."]
+                  f"{rf['alg_bytes_per_launch']/1e9:.3f} GB algorithmic per launch "
+                  f"({rf['alg_achieved']:.0f} GB/s, {100*rf['alg_frac']:.1f}% of 8 TB/s without cache credit)."]
     out = os.path.join(ROOT, "profiles", f"k_accum_{args.workload}.md")
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
