@@ -280,6 +280,25 @@ tf_status tf_foldin(tf_ctx *ctx, int32_t mode, int32_t nreq, const int64_t *h_re
                     const int32_t *d_idx, const double *d_vals, int32_t method, int32_t sweeps,
                     double *d_rows);
 
+/*
+ * tf_foldin_noalloc -- tf_foldin for callers that cannot allocate memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): same arguments, semantics, results (bit for bit) and errors,
+ * but the call allocates nothing (no device memory; no host memory either,
+ * error messages included).  Its
+ * workspace (the products P, chunk tables and partial Gram records, failure
+ * flags) lives in one fixed array of 32 MiB per GPU, which the library
+ * reserves when it is loaded and holds until the process ends.
+ * TF_E_INVALID (message names the bytes needed) for a batch whose workspace
+ * exceeds it: about 32 MiB / (K * 4 + 300) entries in FP32, e.g. ~80,000
+ * entries at K = 100.  Every call on one GPU uses the same array and it
+ * keeps the last call's contents: calls that overlap on one GPU (two host
+ * threads, or two streams) race, so the caller serialises them.
+ */
+tf_status tf_foldin_noalloc(tf_ctx *ctx, int32_t mode, int32_t nreq, const int64_t *h_req_ptr,
+                            const int32_t *d_idx, const double *d_vals, int32_t method,
+                            int32_t sweeps, double *d_rows);
+
 /* ------------------------------------------------------------------ */
 /* Fold-in serving: requests arrive one at a time from any host thread; a
  * scheduler packs whatever is queued into a batch when a stream slot is free

@@ -60,6 +60,10 @@ inline void fold_chunk_tables(const int64_t *h_req_ptr, int64_t nreq, int32_t *f
 }
 
 size_t fold_full_lds(int K, int prec);
+// Device address of the fold-in scratch array on `device` (looked up once,
+// with that device current); its size in bytes.
+hipError_t fold_scratch_setup(int device);
+size_t fold_scratch_bytes();
 // Validation must complete (and pass) before compute: the compute kernels
 // index the factors with the request's indices.
 hipError_t launch_fold_validate(const FoldArgs &a, int64_t total, const int64_t *dims,

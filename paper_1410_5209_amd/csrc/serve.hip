@@ -669,3 +669,197 @@ tf_status tf_foldin(tf_ctx *ctx, int32_t mode, int32_t nreq, const int64_t *h_re
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ fold-in without allocation
+// tf_foldin_noalloc runs the kernels of tf_foldin with its workspace in one
+// file-scope device array per GPU instead of memory it allocates.  In host
+// code the array's name is only a stand-in: its device address is looked up
+// once per device (fold_scratch_setup, called by tf_init with the device
+// current) and only that address is handed to kernels.
+namespace {
+
+constexpr size_t kFoldScratchBytes = (size_t)32 << 20;   // per device
+constexpr int kScratchDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) char scratch[kFoldScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchDevices] = {nullptr};
+
+void *scratch_of(int device)
+{
+    if (device < 0 || device >= kScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
+// chunk_first (nreq + 1) and chunk_req of a batch from its entry offsets, by
+// one workgroup: per tile of 256 requests, an inclusive scan of the chunk
+// counts in LDS, offset by the running total of the earlier tiles.
+__global__ __launch_bounds__(256) void k_fold_tables(const int64_t *req_ptr, int32_t nreq,
+                                                     int32_t *first, int32_t *req)
+{
+    __shared__ int32_t sc[256];
+    __shared__ int32_t base;
+    const int tid = threadIdx.x;
+    if (tid == 0) base = 0;
+    __syncthreads();
+    for (int32_t q0 = 0; q0 < nreq; q0 += 256) {
+        const int32_t q = q0 + tid;
+        const int32_t cnt = q < nreq
+            ? (int32_t)((req_ptr[q + 1] - req_ptr[q] + kFoldChunkEntries - 1) / kFoldChunkEntries) : 0;
+        sc[tid] = cnt;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            const int32_t v = tid >= off ? sc[tid - off] : 0;
+            __syncthreads();
+            sc[tid] += v;
+            __syncthreads();
+        }
+        const int32_t excl = base + sc[tid] - cnt;
+        if (q < nreq) {
+            first[q] = excl;
+            for (int32_t t = 0; t < cnt; ++t) req[excl + t] = q;
+        }
+        __syncthreads();
+        if (tid == 255) base += sc[255];
+        __syncthreads();
+    }
+    if (tid == 0) first[nreq] = base;
+}
+
+// The failure flags start at "none" (a fill kernel rather than a memset).
+__global__ void k_fold_flags_init(unsigned long long *flags)
+{
+    if (threadIdx.x < 2) flags[threadIdx.x] = ~0ull;
+}
+
+}  // namespace
+
+namespace tfk {
+
+hipError_t fold_scratch_setup(int device)
+{
+    if (device < 0 || device >= kScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+    return hipSuccess;
+}
+
+size_t fold_scratch_bytes() { return kFoldScratchBytes; }
+
+}  // namespace tfk
+
+extern "C" tf_status tf_foldin_noalloc(tf_ctx *ctx, int32_t mode, int32_t nreq,
+                                       const int64_t *h_req_ptr, const int32_t *d_idx,
+                                       const double *d_vals, int32_t method, int32_t sweeps,
+                                       double *d_rows)
+{
+    if (!ctx) return TF_E_INVALID;
+    auto fail = [&](tf_status st, const char *msg) { ctx->err = msg; return st; };
+    if (mode < 0 || mode >= ctx->N || nreq < 0 || (nreq > 0 && (!h_req_ptr || !d_rows)))
+        return fail(TF_E_INVALID, "bad mode, nreq or NULL pointer");
+    if (method != TF_FOLDIN_FULL && method != TF_FOLDIN_CDTF) return fail(TF_E_INVALID, "bad method");
+    if (method == TF_FOLDIN_CDTF && sweeps < 1) return fail(TF_E_INVALID, "sweeps must be >= 1");
+    if (method == TF_FOLDIN_FULL && ctx->K > kFoldMaxKFull)
+        return fail(TF_E_UNSUPPORTED, "full-rank fold-in supports K <= 128");
+    if (nreq == 0) return TF_OK;
+    if (h_req_ptr[0] != 0) return fail(TF_E_INVALID, "h_req_ptr[0] must be 0");
+    int64_t nchunks = 0;
+    for (int32_t q = 0; q < nreq; ++q) {
+        if (h_req_ptr[q + 1] < h_req_ptr[q]) return fail(TF_E_INVALID, "h_req_ptr must be non-decreasing");
+        nchunks += (h_req_ptr[q + 1] - h_req_ptr[q] + kFoldChunkEntries - 1) / kFoldChunkEntries;
+    }
+    const int64_t total = h_req_ptr[nreq];
+    if (total > 0 && (!d_idx || !d_vals)) return fail(TF_E_INVALID, "NULL entries");
+    if (ctx->stale) return fail(TF_E_STATE, "factors were set; call tf_resync first");
+    char *base = static_cast<char *>(scratch_of(ctx->device));
+    if (!base) return fail(TF_E_STATE, "no fold-in scratch on this context's device");
+
+    // layout in the scratch array: req_ptr | chunk_first | chunk_req | P | r |
+    // partial Grams | flags
+    const bool gram = fold_uses_gram(ctx->K);
+    if (!gram) nchunks = 0;
+    const size_t gs_bytes = (size_t)fold_gram_stride(ctx->K) * ta_bytes(ctx->prec);
+    const size_t o_ptr = 0;
+    const size_t o_first = o_ptr + align256((size_t)(nreq + 1) * 8);
+    const size_t o_creq = o_first + align256((size_t)(nreq + 1) * 4);
+    const size_t o_P = o_creq + align256((size_t)nchunks * 4);
+    const size_t o_r = o_P + align256((size_t)total * ctx->K * ta_bytes(ctx->prec));
+    const size_t o_g = o_r + align256(gram ? 0 : (size_t)total * 8);
+    const size_t o_flags = o_g + align256((size_t)nchunks * gs_bytes);
+    const size_t need = o_flags + 256;
+    if (need > kFoldScratchBytes) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "fold-in batch needs %zu bytes of workspace; the scratch holds %zu",
+                 need, kFoldScratchBytes);
+        return fail(TF_E_INVALID, buf);
+    }
+    int64_t *d_ptr = reinterpret_cast<int64_t *>(base + o_ptr);
+    unsigned long long *flags = reinterpret_cast<unsigned long long *>(base + o_flags);
+
+    FoldArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.N = ctx->N; a.mode = mode; a.K = ctx->K; a.nreq = nreq;
+    a.req_ptr = d_ptr; a.oidx = d_idx; a.vals = d_vals;
+    for (int n = 0; n < ctx->N; ++n) a.A[n] = ctx->m[n].A;
+    a.P = base + o_P;
+    a.r = gram ? nullptr : reinterpret_cast<double *>(base + o_r);
+    a.rows = d_rows;
+    a.lambda = ctx->lambda; a.reg_mode = ctx->opt.reg_mode; a.sweeps = sweeps;
+    a.bad = flags; a.bad_req = flags + 1;
+    a.chunk_first = reinterpret_cast<int32_t *>(base + o_first);
+    a.chunk_req = reinterpret_cast<int32_t *>(base + o_creq);
+    a.nchunks = (int32_t)nchunks;
+    a.gpart = base + o_g;
+
+    tf_status st = TF_OK;
+    unsigned long long hf[2] = {0, 0};
+    hipStream_t s = ctx->stream;
+    hipError_t e = hipMemcpyAsync(d_ptr, h_req_ptr, (size_t)(nreq + 1) * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && gram) {
+        hipLaunchKernelGGL(k_fold_tables, dim3(1), dim3(256), 0, s, d_ptr, nreq,
+                           reinterpret_cast<int32_t *>(base + o_first),
+                           reinterpret_cast<int32_t *>(base + o_creq));
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_fold_flags_init, dim3(1), dim3(64), 0, s, flags);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = launch_fold_validate(a, total, ctx->dims, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(hf, flags, sizeof hf, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && hf[0] != ULLONG_MAX) {
+        char buf[128];
+        snprintf(buf, sizeof buf, "fold-in entry %llu has a bad index or value", hf[0]);
+        ctx->err = buf;
+        st = TF_E_INVALID;
+    }
+    if (e == hipSuccess && st == TF_OK) {
+        e = launch_fold_compute(ctx->prec, a, total, method, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(hf, flags, sizeof hf, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e == hipSuccess && hf[1] != ULLONG_MAX) {
+            char buf[128];
+            snprintf(buf, sizeof buf, "fold-in request %llu: non-positive Cholesky pivot (row set to 0)", hf[1]);
+            ctx->err = buf;
+            st = TF_E_NUMERIC;
+        }
+    }
+    if (e != hipSuccess) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "fold-in: %s", hipGetErrorString(e));
+        ctx->err = buf;
+        return TF_E_DEVICE;
+    }
+    return st;
+}

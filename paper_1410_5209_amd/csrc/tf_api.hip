@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 
+#include "foldin.h"
 #include "tf_internal.h"
 
 using namespace tfk;
@@ -852,6 +853,10 @@ tf_status tf_init(tf_ctx **out, int32_t N, const int64_t *dims, int64_t nnz, con
     int dev = 0;
     hipError_t he = hipGetDevice(&dev);
     if (he != hipSuccess) return set_err(&g_init_err, TF_E_DEVICE, "no HIP device: %s", hipGetErrorString(he));
+    // the device address of tf_foldin_noalloc's scratch array, once per device
+    he = fold_scratch_setup(dev);
+    if (he != hipSuccess)
+        return set_err(&g_init_err, TF_E_DEVICE, "fold-in scratch lookup: %s", hipGetErrorString(he));
 
     tf_ctx *c = new (std::nothrow) tf_ctx();
     if (!c) return set_err(&g_init_err, TF_E_NOMEM, "host allocation failed");
@@ -863,6 +868,7 @@ tf_status tf_init(tf_ctx **out, int32_t N, const int64_t *dims, int64_t nnz, con
     c->prec = o.precision;
     c->stream = (hipStream_t)o.stream;
     c->device = dev;
+    c->err.reserve(512);   // messages up to this length are set without allocating
     for (int n = 0; n < N; ++n) c->dims[n] = dims[n];
     tf_status s = build_state(c, d_idx, d_vals);
     if (s != TF_OK) {

@@ -127,6 +127,7 @@ def lib():
         L.tf_profile_read.argtypes = [P, ctypes.POINTER(tf_kstats)]
         L.tf_plan_rows.argtypes = [P, i64, i32, i32, i32, i32, ctypes.POINTER(tf_plan_summary)]
         L.tf_foldin.argtypes = [P, i32, i32, P, P, P, i32, i32, P]
+        L.tf_foldin_noalloc.argtypes = [P, i32, i32, P, P, P, i32, i32, P]
         L.tf_autotune.argtypes = [P, i32, P, i32, i32, ctypes.POINTER(tf_tune_result)]
         L.tf_serve_default_options.argtypes = [ctypes.POINTER(tf_serve_opts)]
         L.tf_serve_default_options.restype = None
@@ -147,7 +148,7 @@ def lib():
                      "tf_loss", "tf_predict", "tf_get_factor", "tf_get_factor_block", "tf_set_factor",
                      "tf_resync",
                      "tf_get_residual", "tf_get_csr", "tf_profile", "tf_profile_read",
-                     "tf_plan_rows", "tf_foldin", "tf_serve_open", "tf_serve_submit",
+                     "tf_plan_rows", "tf_foldin", "tf_foldin_noalloc", "tf_serve_open", "tf_serve_submit",
                      "tf_serve_wait", "tf_serve_replay", "tf_serve_report",
                      "tf_serve_reset_stats", "tf_autotune"):
             getattr(L, name).restype = ctypes.c_int32
