@@ -59,6 +59,12 @@ typedef int32_t tf_status;
                                 trial passes (as tf_autotune with the one
                                 candidate C, tune_tiles = 1) before the first
                                 split of each new compute width */
+#define TF_STRATEGY_PERSISTENT 3  /* SKEW's plan in one persistent launch per
+                                pass: as many workgroups as the GPU holds at
+                                once, whose wavefronts take the tasks (chunks
+                                of the longest rows first, then groups of
+                                shorter rows) from a counter until none is
+                                left; same results as SKEW, bit for bit */
 
 /* Column order of tf_sweep (Algorithm 1 draws each split's columns without
  * replacement; Section 3.1 keeps a fixed order for CDTF). */
@@ -396,8 +402,9 @@ tf_status tf_profile_read(tf_ctx *ctx, tf_kstats *out);    /* synchronises */
 /* Measurement probe (not part of the method): the rate of random 128-byte
  * row gathers, the requests the row passes of a split are bound by.
  *   d_table  device, rows x 32 floats (128-byte rows)
+ *   rows     1 <= rows <= 2^32
  *   waves    wavefronts launched, a multiple of 4 (>= 4); each half
- *            wavefront reads `steps` rows (a multiple of 8), chosen by a
+ *            wavefront reads `steps` rows (a multiple of 32), chosen by a
  *            SplitMix64-style hash of (seed, wave, step, half)
  *   d_out    device, waves x 64 floats (one running sum per lane)
  *   ms       out: HIP-event time of the launch on `stream`

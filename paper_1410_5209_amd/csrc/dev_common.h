@@ -185,36 +185,25 @@ __device__ __forceinline__ void group_reduce(T (&v)[NE], int G)
     }
 }
 
+// Persistent launches: the next task index for the calling wavefront (all
+// 64 lanes active), taken by lane 0 from the launch's work counter.
+__device__ __forceinline__ int take_task(unsigned int *work)
+{
+    int t = 0;
+    if ((threadIdx.x & 63) == 0) t = (int)atomicAdd(work, 1u);
+    return __shfl(t, 0, 64);
+}
+
 // A sweep stops updating factors after the first mode pass that meets a
 // non-positive pivot (the rows of that pass that solved are kept), as the
 // oracle's split loop does.  flags[0..kMaxModes) hold the smallest failing
-// row per mode, flags[kStopWord] is the sticky stop flag, flags[kCountWord]
-// counts the blocks of the running solve launch.  pass_halted is read by a
-// solve block before any write: a launch sees the flag of earlier passes
-// only, because only its own last block can set it (pass_latch).
+// row per mode and flags[kStopWord] the sticky stop flag.  A solve launch
+// reads the stop flag before any write (pass_halted); the flag is raised
+// only by the one-lane kernel k_pass_latch launched after each pass's
+// solves, so a launch sees the failures of earlier passes only.
 __device__ __forceinline__ bool pass_halted(const unsigned long long *flags)
 {
     return __hip_atomic_load(flags + kStopWord, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0ull;
-}
-
-// Called by every block of a solve launch after its writes (all threads):
-// the last block to finish raises the stop flag if any mode recorded a
-// failure, and clears the block count for the next launch.
-__device__ __forceinline__ void pass_latch(unsigned long long *flags, int nmodes)
-{
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned long long prev = atomicAdd(flags + kCountWord, 1ull);
-        if (prev == (unsigned long long)(gridDim.x - 1)) {
-            __threadfence();
-            bool any = false;
-            for (int n = 0; n < nmodes; ++n)
-                any = any || __hip_atomic_load(flags + n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ~0ull;
-            if (any) atomicExch(flags + kStopWord, 1ull);
-            atomicExch(flags + kCountWord, 0ull);
-        }
-    }
 }
 
 }  // namespace tfk

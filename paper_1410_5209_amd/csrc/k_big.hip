@@ -255,7 +255,6 @@ __global__ __launch_bounds__(256) void k_big_rows(BigArgs a)
             for (int k = tid; k < C; k += 64) arow[cols[k]] = store_cast<TS>(rhs[k]);
         }
     }
-    pass_latch(a.flags, a.nmodes);
 }
 
 // R-hat of a split on mode 1's copy (position q in mode 1's CSR order, entry

@@ -243,4 +243,20 @@ hipError_t launch_predict(int prec, int N, int K, const void *const *A, const in
     return hipGetLastError();
 }
 
+// After a pass's solves: raise the sweep's stop flag if any mode recorded a
+// non-positive pivot (see pass_halted).
+__global__ void k_pass_latch(unsigned long long *flags, int nmodes)
+{
+    if (threadIdx.x != 0) return;
+    bool any = false;
+    for (int n = 0; n < nmodes; ++n) any = any || flags[n] != ~0ull;
+    if (any) flags[kStopWord] = 1ull;
+}
+
+hipError_t launch_pass_latch(unsigned long long *flags, int nmodes, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pass_latch, dim3(1), dim3(64), 0, st, flags, nmodes);
+    return hipGetLastError();
+}
+
 }  // namespace tfk

@@ -25,14 +25,8 @@ namespace tfk {
 // FM: 0 a plain pass; 1 a split's first pass in which no other mode has
 // been updated yet (the split-start segments S equal W and are not read);
 // 2 a first pass that reads S for the modes already updated.
-// The FM = 1 first pass at C = 10 with two other modes (3-way tensors) is
-// asked for 3 waves per SIMD in FP32 / BF16: it fits 168 registers with 4
-// spilled, where left alone it takes 172 and runs 2 waves.  Other
-// instantiations are left to the compiler (forcing them spills up to
-// hundreds of registers).
 template <int PREC, int CP, int NO, int FM>
-__global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu((FM == 1 && CP == 10 && NO == 2 && PREC != P_F64) ? 3 : 1))) void k_accum(AccumArgs a)
+__global__ __launch_bounds__(256) void k_accum(AccumArgs a)
 {
     constexpr bool FIRST = FM > 0;
     using TS = typename Types<PREC>::TS;
@@ -42,8 +36,10 @@ __attribute__((amdgpu_waves_per_eu((FM == 1 && CP == 10 && NO == 2 && PREC != P_
     constexpr int NEP = gram_stride(CP);
 
     const int lane = threadIdx.x & 63;
-    const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (t >= a.ntasks) return;  // uniform per wavefront
+    // a wavefront's task: by its place in the grid, or (persistent launch)
+    // taken from the work counter until none is left (uniform per wavefront)
+    int t = a.work ? take_task(a.work) : blockIdx.x * 4 + (threadIdx.x >> 6);
+    for (; t < a.ntasks; t = take_task(a.work)) {
     const Task task = a.tasks[t];
     const int G = task.G;
     const int lg = __ffs(G) - 1;
@@ -208,14 +204,8 @@ __attribute__((amdgpu_waves_per_eu((FM == 1 && CP == 10 && NO == 2 && PREC != P_
                     for (int c = 0; c < CP; ++c) ts[c] *= w[l][c];
                 }
             }
-            // R-hat of this split from the previous split's residual state
-            // (summed before the next entry's segments are requested, so the
-            // products' registers are free for them)
-            TA dr = TA(0), ds = TA(0);
-#pragma unroll
-            for (int c = 0; c < CP; ++c) { dr += tp[c]; ds += ts[c]; }
-            const TA r = ((TA)rh - dr) + ds;
-            stream_store((TR)r, rhat + j);
+            const TR rcur = rh;
+            const int64_t jcur = j;
             if (jn < end) {
                 rh = rn;
                 fetch(in_, w, pv, sv);
@@ -226,6 +216,12 @@ __attribute__((amdgpu_waves_per_eu((FM == 1 && CP == 10 && NO == 2 && PREC != P_
                     rn = stream_load(rhat + jnn);
                 }
             }
+            // R-hat of this split from the previous split's residual state
+            TA dr = TA(0), ds = TA(0);
+#pragma unroll
+            for (int c = 0; c < CP; ++c) { dr += tp[c]; ds += ts[c]; }
+            const TA r = ((TA)rcur - dr) + ds;
+            stream_store((TR)r, rhat + jcur);
 
             int e = 0;
 #pragma unroll
@@ -332,6 +328,8 @@ __attribute__((amdgpu_waves_per_eu((FM == 1 && CP == 10 && NO == 2 && PREC != P_
             }
         }
     }
+    if (!a.work) break;
+    }
 }
 
 // Index of B(c1, c2), c1 <= c2, in the packed upper-triangle record.
@@ -416,7 +414,6 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs a)
             if (!solve_row<PREC, CP>(g, lam, o)) atomicMin(a.bad, (unsigned long long)row);
         }
     }
-    pass_latch(a.flags, a.nmodes);
 }
 
 // Sum of the chunk partials of each split row into the row's Gram record.

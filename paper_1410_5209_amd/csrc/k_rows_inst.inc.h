@@ -5,20 +5,36 @@
 #include "k_rows.inc.h"
 #include "k_rows_wide.inc.h"
 
+#include <algorithm>
+
 namespace tfk {
+
+// Launch of a row-accumulation kernel: a grid of one wavefront per task, or
+// (persistent launch, a.work set) as many workgroups as the GPU holds at
+// once, whose wavefronts take tasks from the work counter.
+template <typename F>
+static hipError_t launch_rows(F *kernel, const AccumArgs &a, int grid, hipStream_t st)
+{
+    if (a.work) {
+        int per_cu = 0, dev = 0, cus = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0);
+        if (e == hipSuccess) e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        grid = std::max(1, std::min(grid, per_cu * cus));
+    }
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
 
 template <int PREC, int CP, int NO>
 static hipError_t accum_no(bool first, const AccumArgs &a, int grid, hipStream_t st)
 {
     bool any_before = false;
     for (int l = 0; l < NO; ++l) any_before |= a.before[l] != 0;
-    if (first && any_before)
-        hipLaunchKernelGGL((k_accum<PREC, CP, NO, 2>), dim3(grid), dim3(256), 0, st, a);
-    else if (first)
-        hipLaunchKernelGGL((k_accum<PREC, CP, NO, 1>), dim3(grid), dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_accum<PREC, CP, NO, 0>), dim3(grid), dim3(256), 0, st, a);
-    return hipGetLastError();
+    if (first && any_before) return launch_rows(k_accum<PREC, CP, NO, 2>, a, grid, st);
+    if (first) return launch_rows(k_accum<PREC, CP, NO, 1>, a, grid, st);
+    return launch_rows(k_accum<PREC, CP, NO, 0>, a, grid, st);
 }
 
 template <int PREC, int CP>
@@ -58,13 +74,9 @@ static hipError_t accum_wide_no(bool first, const AccumArgs &a, int grid, hipStr
 {
     bool any_before = false;
     for (int l = 0; l < NO; ++l) any_before |= a.before[l] != 0;
-    if (first && any_before)
-        hipLaunchKernelGGL((k_accum_wide<PREC, NO, 2>), dim3(grid), dim3(256), 0, st, a);
-    else if (first)
-        hipLaunchKernelGGL((k_accum_wide<PREC, NO, 1>), dim3(grid), dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_accum_wide<PREC, NO, 0>), dim3(grid), dim3(256), 0, st, a);
-    return hipGetLastError();
+    if (first && any_before) return launch_rows(k_accum_wide<PREC, NO, 2>, a, grid, st);
+    if (first) return launch_rows(k_accum_wide<PREC, NO, 1>, a, grid, st);
+    return launch_rows(k_accum_wide<PREC, NO, 0>, a, grid, st);
 }
 
 template <int PREC, int CP>

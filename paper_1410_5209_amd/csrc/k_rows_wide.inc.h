@@ -82,11 +82,14 @@ __global__ __launch_bounds__(256) void k_accum_wide(AccumArgs a)
     const int lane = threadIdx.x & 63;
     const int half = lane >> 5;
     const int c = lane & 31;
-    const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (t >= a.ntasks) return;  // uniform per wavefront; no block barriers below
-    const Task task = a.tasks[t];
+    // a wavefront's task: by its place in the grid, or (persistent launch)
+    // taken from the work counter until none is left (uniform per
+    // wavefront; no block barriers below)
+    int t = a.work ? take_task(a.work) : blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t ld = a.ld;
     TR *rhat = reinterpret_cast<TR *>(a.rhat);
+    for (; t < a.ntasks; t = take_task(a.work)) {
+    const Task task = a.tasks[t];
 
     const int nrows = task.kind == 0 ? task.count : 1;
     for (int rr = 0; rr < nrows; ++rr) {
@@ -197,6 +200,8 @@ __global__ __launch_bounds__(256) void k_accum_wide(AccumArgs a)
         }
         if (half == 0) out[WNT + c] = rhs;
         if (lane < NEP - WNT - WCP) out[WNT + WCP + lane] = 0.f;
+    }
+    if (!a.work) break;
     }
 }
 
@@ -337,7 +342,6 @@ __global__ __launch_bounds__(256) void k_solve_wide(SolveArgs a)
             o[i] = store_cast<TS>(c);
         }
     }
-    pass_latch(a.flags, a.nmodes);
 }
 
 }  // namespace tfk

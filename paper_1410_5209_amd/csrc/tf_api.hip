@@ -185,7 +185,9 @@ constexpr size_t kSlabRowBytes = 384;
 // Segment width and row stride of the interleaved slabs for a given number
 // of columns: segments of whole 8-byte units (so W and S start 16-byte
 // aligned), rows padded to whole 128-byte lines so that no row straddles a
-// line it does not need.
+// line it does not need.  (Keeping W, P and S in three separate arrays
+// instead, once a segment fills whole lines, was measured on the 5-way
+// workload at C = 32 and changed no pass time.)
 tf_status slab_geometry(tf_ctx *c, int width)
 {
     const int64_t q = c->prec == P_BF16 ? 4 : 2;
@@ -234,6 +236,16 @@ void fill_accum_args(tf_ctx *c, int n, int npend, AccumArgs *a)
     a->ld = c->ld;
     a->gram = c->gram;
     a->gpart = c->gpart;
+    a->work = c->opt.strategy == TF_STRATEGY_PERSISTENT
+                  ? reinterpret_cast<unsigned int *>(c->d_bad + kWorkWord) : nullptr;
+}
+
+// The work counter of a persistent launch starts at zero (a stream-ordered
+// clear before each launch).
+tf_status reset_work(tf_ctx *c, const AccumArgs &a)
+{
+    if (a.work) HIPCHK(c, hipMemsetAsync(a.work, 0, sizeof(unsigned int), c->stream));
+    return TF_OK;
 }
 
 hipEvent_t take_event(tf_ctx *c)
@@ -453,6 +465,7 @@ tf_status run_split_big(tf_ctx *c, const int32_t *cols, int ncols, int T_in)
                 HIPCHK(c, hipEventRecord(e1, c->stream));
                 c->ev_pending.push_back(tf_ctx::Timed{e0, e1, alg_bytes(c, n, ncols, 0, false), false});
             }
+            HIPCHK(c, launch_pass_latch(c->d_bad, c->N, c->stream));
         }
     }
     c->pend.assign(cols, cols + ncols);
@@ -502,6 +515,8 @@ tf_status run_split(tf_ctx *c, const int32_t *cols, int ncols, int T_in)
             }
             const int grid = (md.ntasks + 3) / 4;
             if (grid > 0) {
+                tf_status s0 = reset_work(c, a);
+                if (s0 != TF_OK) return s0;
                 hipEvent_t e0 = nullptr, e1 = nullptr;
                 if (c->profiling) {
                     e0 = take_event(c);
@@ -530,6 +545,7 @@ tf_status run_split(tf_ctx *c, const int32_t *cols, int ncols, int T_in)
             sa.flags = c->d_bad;
             sa.nmodes = c->N;
             HIPCHK(c, launch_solve(c->prec, CP, sa, c->stream));
+            HIPCHK(c, launch_pass_latch(c->d_bad, c->N, c->stream));
         }
     }
     for (int l = 0; l < c->N; ++l) {
@@ -836,7 +852,8 @@ tf_status tf_init(tf_ctx **out, int32_t N, const int64_t *dims, int64_t nnz, con
     }
     if (o.precision < 0 || o.precision > 2) return set_err(&g_init_err, TF_E_INVALID, "bad precision");
     if (o.reg_mode != 0 && o.reg_mode != 1) return set_err(&g_init_err, TF_E_INVALID, "bad reg_mode");
-    if (o.strategy != TF_STRATEGY_PLAIN && o.strategy != TF_STRATEGY_SKEW && o.strategy != TF_STRATEGY_AUTO)
+    if (o.strategy != TF_STRATEGY_PLAIN && o.strategy != TF_STRATEGY_SKEW && o.strategy != TF_STRATEGY_AUTO &&
+        o.strategy != TF_STRATEGY_PERSISTENT)
         return set_err(&g_init_err, TF_E_INVALID, "bad strategy");
     if (o.col_order != TF_ORDER_FIXED && o.col_order != TF_ORDER_RANDOM)
         return set_err(&g_init_err, TF_E_INVALID, "bad col_order");
@@ -986,7 +1003,11 @@ tf_status time_pass(tf_ctx *c, int n, int CP, int npend, bool first, void *rhat,
     if (!e0 || !e1) return CTX_FAIL(c, TF_E_DEVICE, "event creation failed");
     HIPCHK(c, hipEventRecord(e0, c->stream));
     const int grid = (md.ntasks + 3) / 4;
-    if (grid > 0) HIPCHK(c, launch_accum(c->prec, CP, c->N - 1, first, a, grid, c->stream));
+    if (grid > 0) {
+        tf_status s0 = reset_work(c, a);
+        if (s0 != TF_OK) return s0;
+        HIPCHK(c, launch_accum(c->prec, CP, c->N - 1, first, a, grid, c->stream));
+    }
     if (md.nsplit > 0)
         HIPCHK(c, launch_chunk_reduce(c->prec, CP, md.split_rows, md.split_chunk_ptr, md.nsplit,
                                       c->gpart, c->gram, c->stream));

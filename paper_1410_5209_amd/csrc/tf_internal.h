@@ -25,10 +25,11 @@ struct bf16 {
 // precisions), 32 for the wide kernels (FP32 and BF16 storage).
 constexpr int kMaxC = 32;
 constexpr int kMaxModes = 8;
-// Words of the failure flags after the per-mode failing rows (see pass_latch).
+// Words of the failure flags after the per-mode failing rows (see pass_halted).
 constexpr int kStopWord = kMaxModes;
 constexpr int kCountWord = kMaxModes + 1;
-constexpr int kFlagWords = kMaxModes + 2;
+constexpr int kWorkWord = kMaxModes + 2;   // task counter of persistent launches
+constexpr int kFlagWords = kMaxModes + 3;
 
 // Gram record of one row: upper triangle of B (c1 <= c2, row-major) then the
 // right-hand side c; padded to a multiple of 4 entries.
@@ -60,6 +61,8 @@ struct AccumArgs {
     int64_t ld;                          // slab row stride (elements)
     void *gram;                          // per-row Gram records
     void *gpart;                         // per-chunk partial Gram records
+    unsigned int *work;                  // non-null: persistent launch, tasks taken
+                                         // from this counter (zero at launch)
 };
 
 struct SolveArgs {
@@ -125,6 +128,7 @@ int64_t big_record_stride(int C);
 hipError_t launch_accum(int prec, int CP, int no, bool first, const AccumArgs &a, int grid,
                         hipStream_t st);
 hipError_t launch_solve(int prec, int CP, const SolveArgs &a, hipStream_t st);
+hipError_t launch_pass_latch(unsigned long long *flags, int nmodes, hipStream_t st);
 hipError_t launch_chunk_reduce(int prec, int CP, const int32_t *split_rows,
                                const int32_t *split_chunk_ptr, int nsplit, const void *gpart,
                                void *gram, hipStream_t st);
@@ -248,7 +252,7 @@ struct tf_ctx {
     void *gpart = nullptr;    // max_chunks x gram_stride(slab_cp) (TA)
     size_t gpart_bytes = 0;   // its size
     int32_t *d_cols = nullptr;  // device copy of split columns + pending columns
-    unsigned long long *d_bad = nullptr;  // kFlagWords failure flags (pass_latch)
+    unsigned long long *d_bad = nullptr;  // kFlagWords failure flags (pass_halted)
     double *d_partials = nullptr;
     int64_t partials_cap = 0;
     double *d_scalar = nullptr;

@@ -17,7 +17,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "tf.h")
 
 TF_OK, TF_E_INVALID, TF_E_NOMEM, TF_E_DEVICE, TF_E_NUMERIC, TF_E_UNSUPPORTED, TF_E_BUSY, TF_E_STATE = range(8)
 TF_PREC_F64, TF_PREC_F32, TF_PREC_BF16 = 0, 1, 2
-TF_STRATEGY_PLAIN, TF_STRATEGY_SKEW, TF_STRATEGY_AUTO = 0, 1, 2
+TF_STRATEGY_PLAIN, TF_STRATEGY_SKEW, TF_STRATEGY_AUTO, TF_STRATEGY_PERSISTENT = 0, 1, 2, 3
 TF_RESID_AUTO, TF_RESID_OWN, TF_RESID_SHARED = 0, 1, 2
 TF_ORDER_FIXED, TF_ORDER_RANDOM = 0, 1
 

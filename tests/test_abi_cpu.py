@@ -76,7 +76,7 @@ def test_init_rejects_bad_arguments_on_host():
         assert st == tf.TF_E_INVALID, (N, nnz, K, lam)
         assert ctx.value is None
         assert len(tf.tf_last_error(None)) > 0
-    bad_opts = [tf.tf_default_options(precision=7), tf.tf_default_options(strategy=3),
+    bad_opts = [tf.tf_default_options(precision=7), tf.tf_default_options(strategy=4),
                 tf.tf_default_options(col_order=2), tf.tf_default_options(resid_share=5)]
     half = tf.tf_default_options()
     half.dev_alloc = tf.ALLOC_FN(lambda n, s, u: None)   # dev_free left NULL

@@ -87,3 +87,24 @@ def test_memory_budget_refuses_what_does_not_fit():
     g = SparseCP(dims, idx, x, K, 0.4, mem_budget=64 << 20)
     g.sweep(8, 1)
     g.close()
+
+
+@pytest.mark.parametrize("C", [10, 32])
+def test_persistent_launch_gives_the_skew_results_bit_for_bit(C):
+    """TF_STRATEGY_PERSISTENT runs the same plan with workgroups that take
+    tasks from a counter: every task is the same work in the same order, so
+    factors and residual equal the grid launch's bit for bit."""
+    from paper_1410_5209_amd import tf
+    dims, K = [900, 700, 500], 40
+    note(f"persistent launch C={C}")
+    idx, x, A = problem(370 + C, dims, 60000, K, dist="zipf", dedupe="drop")
+    runs = []
+    for strat in (tf.TF_STRATEGY_SKEW, tf.TF_STRATEGY_PERSISTENT):
+        g, _ = pair(dims, idx, x, A, K, 0.5, "f32", strategy=strat, split_threshold=512,
+                    chunk_nnz=128)
+        g.sweep(C, 2)
+        runs.append((g.factors(), g.residual()))
+        g.close()
+    for a, b in zip(runs[0][0], runs[1][0]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(runs[0][1], runs[1][1])
