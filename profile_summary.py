@@ -8,7 +8,9 @@ Reads
                  TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum` run
   --writes CSV   counter_collection.csv of a `--pmc TCC_EA0_WRREQ_sum
                  TCC_EA0_WRREQ_64B_sum TCC_HIT_sum TCC_MISS_sum` run
-and writes
+or, with --ceiling FILE (the JSON line of `bench.py --gather-ceiling`),
+writes profiles/gather_ceiling.{json,md} and nothing else;
+otherwise writes
   profiles/k_accum_<workload>.md          per-kernel durations and traffic
   profiles/k_accum_<workload>_traffic.json bytes per launch of the row-
                                            accumulation kernels, tagged with
@@ -100,11 +102,38 @@ def timed_launches(stats_dir, n):
     return sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in last) / len(last) / 1e3
 
 
+def write_ceiling(path, cmd):
+    """The random-gather ceiling (tf_probe_gather by table size) as JSON for
+    bench.py and as a short table."""
+    with open(path) as f:
+        c = json.loads([l for l in f if l.startswith("{")][-1])["gather_ceiling"]
+    c["command"] = cmd
+    with open(os.path.join(ROOT, "profiles", "gather_ceiling.json"), "w") as f:
+        json.dump(c, f, indent=1)
+    lines = ["# Random 128-byte row gathers by table size (tf_probe_gather)", "",
+             f"Command: `{cmd}`", "",
+             f"{c['waves']} wavefronts, {c['rows_per_half_wave']} rows per half-wavefront, one "
+             "coalesced 128-byte load per row and half-wavefront, rows drawn by a counter-based "
+             "hash (no index stream); median of 5 timed launches after one warm-up.", "",
+             "| table | median ms | G lines/s | GB/s |", "|---|---|---|---|"]
+    for r in c["tables"]:
+        lines.append(f"| {r['table_mb']} MB | {r['median_ms']:.2f} | {r['glines_s']:.1f} | "
+                     f"{r['gbytes_s']:.0f} |")
+    lines += ["", f"Ceiling used for the row passes' L2-miss line rate: {c['ceiling_glines_s']:.1f} "
+              f"G lines/s ({c['ceiling_table']} table: far above the 8 x 4 MB of L2 and the "
+              "256 MB last-level cache)."]
+    with open(os.path.join(ROOT, "profiles", "gather_ceiling.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(os.path.join(ROOT, "profiles", "gather_ceiling.md"))
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--stats", required=True)
-    ap.add_argument("--workload", required=True)
-    ap.add_argument("--stats-cmd", required=True)
+    ap.add_argument("--ceiling", default=None)
+    ap.add_argument("--ceiling-cmd", default="python3 bench.py --gather-ceiling")
+    ap.add_argument("--stats")
+    ap.add_argument("--workload")
+    ap.add_argument("--stats-cmd")
     ap.add_argument("--fetch")
     ap.add_argument("--write")
     ap.add_argument("--fetch-cmd", default="")
@@ -119,6 +148,11 @@ def main():
     ap.add_argument("--last", type=int, default=0,
                     help="average only the last N accumulation launches of each counter run")
     args = ap.parse_args()
+    if args.ceiling:
+        write_ceiling(args.ceiling, args.ceiling_cmd)
+        return
+    if not (args.stats and args.workload and args.stats_cmd):
+        ap.error("--stats, --workload and --stats-cmd are required without --ceiling")
 
     from bench import kernel_source_hash
 
