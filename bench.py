@@ -134,6 +134,45 @@ def cpu_baseline(w, scale, C, reg_mode=0, scale_1t=None):
     return out
 
 
+def foldin_cpu_baseline(m, w, nreq=2000, sweeps=3):
+    """The oracle's fold-in (full rank and CDTF x sweeps) on `nreq` requests of
+    the serving recipe against the same trained factors, with one thread and
+    with one request per host thread at a time (the oracle's fold-in is serial
+    and reads the context only)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    import synth
+    from oracle import oracle as orc
+
+    orc.set_threads(1)
+    # a one-entry tensor of the same shape carries the trained factors
+    o = orc.Oracle(w.dims, np.zeros((1, w.N), dtype=np.int32), np.ones(1), w.K, w.lam)
+    for n in range(w.N):
+        o.set_factor(n, m.factor(n))
+    ptr, oidx, vals = synth.make_requests(w.dims, w.R, nreq, seed=synth.SEED_REQ + 7)
+    reqs = [(oidx[ptr[q]:ptr[q + 1]], vals[ptr[q]:ptr[q + 1]]) for q in range(nreq)]
+    allc = os.cpu_count() or 1
+    out = {"kind": "oracle", "host": host_info(),
+           "sample": f"{nreq} requests of the serving recipe (mean {ptr[-1] / nreq:.0f} entries), "
+                     "solved offline (no arrival process)"}
+    for name, fn in (("full-rank", lambda r: o.foldin_full(0, r[0], r[1])),
+                     (f"cdtf x{sweeps}", lambda r: o.foldin_cdtf(0, r[0], r[1], sweeps))):
+        t0 = time.perf_counter()
+        for r in reqs[: max(nreq // 8, 1)]:
+            fn(r)
+        one = max(nreq // 8, 1) / (time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(allc) as ex:
+            list(ex.map(fn, reqs))
+        many = nreq / (time.perf_counter() - t0)
+        out[name] = {"solves_per_s": many, "cores": allc, "one_thread_solves_per_s": one}
+        log(f"oracle fold-in {name}: {one:.0f} solves/s on 1 thread, {many:.0f} on {allc}")
+    del o
+    return out
+
+
 def roofline(ks, dt_s, workload, C):
     """Bounded HBM figure (counter bytes / live launch time), the algorithmic
     figure beside it, and the L2-miss line rate against the gather ceiling."""
@@ -279,6 +318,7 @@ def run_workload(w, args, steps, warmup, serve=False):
     log(f"{w.name}: timed {steps} sweeps in {dt:.3f} s ({ms:.1f} ms/sweep); loss {loss:.6g} rmse {rmse:.6g}")
     rec = {"workload": w.name, "N": w.N, "dims": w.dims, "nnz": m.nnz, "K": w.K, "C": C,
            "T_in": w.T_in, "lambda": w.lam, "precision": w.prec, "autotune": tinfo,
+           "strategy": args.strategy,
            "steps": steps, "warmup": warmup, "ms_per_step": ms, "value": updates / (ms / 1000.0),
            "roofline": roofline(ks, dt, w.name, C), "loss_after": loss, "train_rmse_after": rmse}
     serving = None
@@ -411,7 +451,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=HEADLINE)
-    ap.add_argument("--strategy", type=int, default=1)
+    ap.add_argument("--strategy", type=int, default=1, choices=[0, 1, 2, 3],
+                    help="row plan: 0 plain, 1 skew-aware, 2 skew-aware with tiles timed, 3 persistent")
     ap.add_argument("--lane-nnz", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", default=None,
@@ -496,7 +537,9 @@ def main():
             log("trained 4 sweeps; serving")
             res = serve_bench(m, w, [1000, 10000, 50000], seconds=0.0, min_requests=100_000,
                               warmup_s=5.0, streams=args.serve_streams, max_batch=args.serve_max_batch)
-            print(json.dumps({"workload": w.name, "serving_full": res}), flush=True)
+            cpu = foldin_cpu_baseline(m, w)
+            print(json.dumps({"workload": w.name, "serving_full": res, "cpu_baseline": cpu}),
+                  flush=True)
             m.close()
         return
 
@@ -537,7 +580,7 @@ def main():
         "config": {"workload": w.name, "N": w.N, "dims": w.dims, "nnz": head["nnz"], "K": w.K,
                    "C": head["C"], "autotune": head["autotune"], "T_in": w.T_in, "lambda": w.lam,
                    "precision": w.prec, "reg_mode": args.reg_mode, "col_order": args.col_order,
-                   "strategy": "skew" if args.strategy == 1 else "plain",
+                   "strategy": {0: "plain", 1: "skew", 2: "auto", 3: "persistent"}[args.strategy],
                    "parallelism": "single-gpu"},
         "roofline": head["roofline"],
         "cpu_baseline": cpu,
