@@ -9,7 +9,8 @@ Reads
   --writes CSV   counter_collection.csv of a `--pmc TCC_EA0_WRREQ_sum
                  TCC_EA0_WRREQ_64B_sum TCC_HIT_sum TCC_MISS_sum` run
 or, with --ceiling FILE (the JSON line of `bench.py --gather-ceiling`),
-writes profiles/gather_ceiling.{json,md} and nothing else;
+writes profiles/gather_ceiling.{json,md} and nothing else; with --serving
+FILE (the JSON line of `bench.py --serve-full`), profiles/serving_<workload>.md;
 otherwise writes
   profiles/k_accum_<workload>.md          per-kernel durations and traffic
   profiles/k_accum_<workload>_traffic.json bytes per launch of the row-
@@ -127,9 +128,39 @@ def write_ceiling(path, cmd):
     print(os.path.join(ROOT, "profiles", "gather_ceiling.md"))
 
 
+def write_serving(path, cmd):
+    """Fold-in serving latency per method and arrival rate, and the oracle's
+    offline solve rate, as a short table."""
+    with open(path) as f:
+        d = json.loads([l for l in f if l.startswith("{")][-1])
+    lines = [f"# Fold-in serving on {d['workload']} factors", "", f"Command: `{cmd}`", "",
+             "Poisson arrivals; latency = submit to the row on the host; requests of the first "
+             "5 s of each schedule are not counted.", "",
+             "| method | rate /s | requests | p50 us | p90 us | p99 us | p99.9 us | solves/s | "
+             "mean batch | failed |", "|---|---|---|---|---|---|---|---|---|---|"]
+    for r in d["serving_full"]:
+        lines.append(f"| {r['method']} | {r['rate_req_s']} | {r['requests']} | {r['p50_us']:.0f} | "
+                     f"{r['p90_us']:.0f} | {r['p99_us']:.0f} | {r['p999_us']:.0f} | "
+                     f"{r['solves_per_s']:.0f} | {r['mean_batch']:.1f} | {r['failed']} |")
+    cpu = d.get("cpu_baseline")
+    if cpu:
+        lines += ["", f"The oracle (FP64, offline, {cpu['sample']}; host {cpu['host'].get('Model name')}, "
+                  f"{cpu['host'].get('nproc')} threads):", ""]
+        for k, v in cpu.items():
+            if isinstance(v, dict) and "solves_per_s" in v:
+                lines.append(f"* {k}: {v['one_thread_solves_per_s']:.0f} solves/s on 1 thread, "
+                             f"{v['solves_per_s']:.0f} on {v['cores']}")
+    out = os.path.join(ROOT, "profiles", f"serving_{d['workload']}.md")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--ceiling", default=None)
+    ap.add_argument("--serving", default=None)
+    ap.add_argument("--serving-cmd", default="python3 bench.py --workload sals-3way-1m-fp32 --serve-full")
     ap.add_argument("--ceiling-cmd", default="python3 bench.py --gather-ceiling")
     ap.add_argument("--stats")
     ap.add_argument("--workload")
@@ -150,6 +181,9 @@ def main():
     args = ap.parse_args()
     if args.ceiling:
         write_ceiling(args.ceiling, args.ceiling_cmd)
+        return
+    if args.serving:
+        write_serving(args.serving, args.serving_cmd)
         return
     if not (args.stats and args.workload and args.stats_cmd):
         ap.error("--stats, --workload and --stats-cmd are required without --ceiling")
