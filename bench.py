@@ -290,7 +290,8 @@ def tune(m, w, cands):
     r = m.autotune(w.T_in, cands, tune_tiles=True)
     info = {"candidates": list(cands), "est_sweep_ms": [r.est_sweep_ms[q] for q in range(r.ncand)],
             "chosen_C": int(r.best_C), "lane_nnz": list(r.lane_nnz)[:w.N],
-            "chunk_nnz": list(r.chunk_nnz)[:w.N], "tune_ms": r.tune_ms}
+            "chunk_nnz": list(r.chunk_nnz)[:w.N], "persistent": list(r.persistent)[:w.N],
+            "tune_ms": r.tune_ms}
     return int(r.best_C), info
 
 

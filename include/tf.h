@@ -240,7 +240,10 @@ tf_status tf_get_csr(tf_ctx *ctx, int32_t n, int64_t *h_rowptr, int32_t *h_perm)
  * packing.  Writes only scratch buffers: the model is unchanged.  With
  * tune_tiles, then re-plans each mode over lanes-per-row targets {1,2,4,8}
  * and chunk lengths {1024,4096,16384} (split threshold twice the chunk) for
- * the chosen C and keeps the fastest plan.  Afterwards tf_sweep(ctx, 0, T_in)
+ * the chosen C and keeps the fastest plan; under TF_STRATEGY_SKEW and
+ * TF_STRATEGY_AUTO it then times that plan with both launch forms (one
+ * wavefront per task, or one resident grid taking tasks from a counter) and
+ * keeps the faster for the mode.  Afterwards tf_sweep(ctx, 0, T_in)
  * uses the chosen C.  Candidates must satisfy 1 <= C <= K and be runnable in
  * the context's precision (C <= 16 in FP64, C <= 16 or C = 32 otherwise;
  * C in 17..31 runs as 32 with zero padding). */
@@ -251,6 +254,10 @@ typedef struct tf_tune_result {
     double est_sweep_ms[16];
     int32_t lane_nnz[8], split_threshold[8], chunk_nnz[8];   /* plan per mode */
     double tune_ms;                                          /* wall time of the tuning */
+    int32_t persistent[8];   /* launch form per mode: 1 = one resident grid taking
+                                tasks from a counter, 0 = one wavefront per task
+                                (chosen with the tiles under TF_STRATEGY_SKEW or
+                                TF_STRATEGY_AUTO; results do not depend on it) */
 } tf_tune_result;
 tf_status tf_autotune(tf_ctx *ctx, int32_t T_in, const int32_t *h_cands, int32_t ncand,
                       int32_t tune_tiles, tf_tune_result *out);

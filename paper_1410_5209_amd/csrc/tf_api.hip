@@ -236,8 +236,7 @@ void fill_accum_args(tf_ctx *c, int n, int npend, AccumArgs *a)
     a->ld = c->ld;
     a->gram = c->gram;
     a->gpart = c->gpart;
-    a->work = c->opt.strategy == TF_STRATEGY_PERSISTENT
-                  ? reinterpret_cast<unsigned int *>(c->d_bad + kWorkWord) : nullptr;
+    a->work = md.persistent ? reinterpret_cast<unsigned int *>(c->d_bad + kWorkWord) : nullptr;
 }
 
 // The work counter of a persistent launch starts at zero (a stream-ordered
@@ -762,6 +761,7 @@ tf_status build_state(tf_ctx *c, const int32_t *d_idx, const double *d_vals)
         md.h_rowptr.assign(rp32.begin(), rp32.end());
         tf_status s = apply_plan(c, n, c->opt.lane_nnz, c->opt.split_threshold, c->opt.chunk_nnz);
         if (s != TF_OK) return s;
+        md.persistent = c->opt.strategy == TF_STRATEGY_PERSISTENT;
     }
 
     // factors (Section 3.1: A^(1) = 0, the others random, so that R = X)
@@ -1141,6 +1141,20 @@ extern "C" tf_status tf_autotune(tf_ctx *ctx, int32_t T_in, const int32_t *h_can
                     if (t < tbest) { tbest = t; bl = lane; bs = 2 * ch; bc = ch; }
                 }
             if ((s = apply_plan(ctx, n, bl, bs, bc)) != TF_OK) return s;
+            // the launch form for these tiles (unless the caller fixed it):
+            // a grid of one wavefront per task, or one resident grid whose
+            // wavefronts take tasks from a counter (same results bit for bit)
+            if (ctx->opt.strategy == TF_STRATEGY_SKEW || ctx->opt.strategy == TF_STRATEGY_AUTO) {
+                double tf_[2];
+                for (int p = 0; p < 2; ++p) {
+                    ctx->m[n].persistent = p == 1;
+                    if ((s = trial_slabs(ctx, bestC, &CP, &npend)) != TF_OK) return s;
+                    double t1 = 0.0, t2 = 0.0;
+                    if ((s = time_mode(ctx, n, CP, npend, T_in, scratch, &t1, &t2)) != TF_OK) return s;
+                    tf_[p] = t1 + (T_in - 1) * t2;
+                }
+                ctx->m[n].persistent = tf_[1] < tf_[0];
+            }
         }
         if ((s = ensure_gram(ctx, pick_cp(bestC, ctx->prec))) != TF_OK) return s;
     }
@@ -1148,6 +1162,7 @@ extern "C" tf_status tf_autotune(tf_ctx *ctx, int32_t T_in, const int32_t *h_can
         out->lane_nnz[n] = ctx->m[n].lane_nnz;
         out->split_threshold[n] = ctx->m[n].split_threshold;
         out->chunk_nnz[n] = ctx->m[n].chunk_nnz;
+        out->persistent[n] = ctx->m[n].persistent ? 1 : 0;
     }
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     out->tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();

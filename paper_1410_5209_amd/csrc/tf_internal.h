@@ -235,6 +235,7 @@ struct tf_ctx {
         int32_t nsplit = 0;
         std::vector<int64_t> h_rowptr;
         int32_t lane_nnz = 0, split_threshold = 0, chunk_nnz = 0;   // plan in use
+        bool persistent = false;        // passes as one resident grid taking tasks
         // residual source of this mode's passes (modes >= 1): its own copy,
         // or mode 0's copy read through pos0 (position in mode-0 order of
         // each entry of this mode's order)

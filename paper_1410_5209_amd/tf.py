@@ -84,7 +84,8 @@ class tf_tune_result(ctypes.Structure):
     _fields_ = [("best_C", ctypes.c_int32), ("ncand", ctypes.c_int32),
                 ("cand_C", ctypes.c_int32 * 16), ("est_sweep_ms", ctypes.c_double * 16),
                 ("lane_nnz", ctypes.c_int32 * 8), ("split_threshold", ctypes.c_int32 * 8),
-                ("chunk_nnz", ctypes.c_int32 * 8), ("tune_ms", ctypes.c_double)]
+                ("chunk_nnz", ctypes.c_int32 * 8), ("tune_ms", ctypes.c_double),
+                ("persistent", ctypes.c_int32 * 8)]
 
 
 class TFError(RuntimeError):

@@ -382,6 +382,7 @@ def test_autotune_leaves_model_unchanged_and_sweeps_with_chosen_width():
     assert res.best_C in (4, 8, 16, 32) and res.ncand == 4
     assert all(res.est_sweep_ms[q] > 0 for q in range(4))
     assert all(res.lane_nnz[n] in (1, 2, 4, 8) for n in range(3))
+    assert all(res.persistent[n] in (0, 1) for n in range(3))
     for n in range(3):
         assert np.array_equal(g.factor(n), F0[n])
     assert np.array_equal(g.residual(), r0)
