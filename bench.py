@@ -203,6 +203,7 @@ def roofline(ks, dt_s, workload, C):
                 "traffic_read": t.get("read_bytes_per_launch"),
                 "traffic_write": t.get("write_bytes_per_launch"),
                 "traffic_fetch_size_calibrated": t.get("fetch_size_bytes_per_launch"),
+                "traffic_dram_destined": t.get("dram_destined_bytes_per_launch"),
                 "l2_hit_rate": t.get("hit_rate")})
     ceil = _profile_json("gather_ceiling.json")
     miss = t.get("l2_misses_per_launch")

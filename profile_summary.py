@@ -8,6 +8,9 @@ Reads
                  TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum` run
   --writes CSV   counter_collection.csv of a `--pmc TCC_EA0_WRREQ_sum
                  TCC_EA0_WRREQ_64B_sum TCC_HIT_sum TCC_MISS_sum` run
+  --dram CSV     counter_collection.csv of a `--pmc TCC_EA0_RDREQ_DRAM_32B_sum
+                 TCC_EA0_WRREQ_WRITE_DRAM_32B_sum` run (the requests the L2
+                 sends towards DRAM, in 32-byte units)
 or, with --ceiling FILE (the JSON line of `bench.py --gather-ceiling`),
 writes profiles/gather_ceiling.{json,md} and nothing else; with --serving
 FILE (the JSON line of `bench.py --serve-full`), profiles/serving_<workload>.md;
@@ -172,6 +175,8 @@ def main():
     ap.add_argument("--reads")
     ap.add_argument("--writes")
     ap.add_argument("--reads-cmd", default="")
+    ap.add_argument("--dram")
+    ap.add_argument("--dram-cmd", default="")
     ap.add_argument("--writes-cmd", default="")
     ap.add_argument("--bench-json", default=None, help="bench.py output line of the same build")
     ap.add_argument("--timed", type=int, default=0,
@@ -253,6 +258,20 @@ def main():
                       f"{(rbytes + wbytes) / 1e3 / t_us:.0f} GB/s of HBM-side traffic "
                       f"({100 * (rbytes + wbytes) / 1e3 / t_us / 8000:.1f}% of 8 TB/s), "
                       f"{miss / 1e3 / t_us:.1f} G L2-miss lines/s."]
+    if args.dram:
+        dr = _last(_per_dispatch(args.dram, _is_accum), args.last)
+        drd = statistics.mean(d.get("TCC_EA0_RDREQ_DRAM_32B_sum", 0) * 32 for d in dr)
+        dwr = statistics.mean(d.get("TCC_EA0_WRREQ_WRITE_DRAM_32B_sum", 0) * 32 for d in dr)
+        traffic.update({"dram_destined_read_bytes_per_launch": drd,
+                        "dram_destined_write_bytes_per_launch": dwr,
+                        "dram_destined_bytes_per_launch": drd + dwr})
+        lines += ["", "## Requests destined for DRAM", "", f"Command: `{args.dram_cmd}`", "",
+                  f"Per accumulation launch: read {drd/1e9:.3f} GB, write {dwr/1e9:.3f} GB towards "
+                  "DRAM (the memory controllers). The 256 MB last-level cache sits on that side, so "
+                  "its hits are still counted: no counter here separates the bytes HBM itself moves."]
+        if "bytes_per_launch" in traffic:
+            lines += ["", f"Against the request-size count above: {(drd + dwr) / traffic['bytes_per_launch']:.4f} "
+                      "of it is DRAM-destined."]
     if args.fetch and args.write:
         fk = statistics.mean(d["FETCH_SIZE"] for d in _last(_per_dispatch(args.fetch, _is_accum), args.last))
         wk = statistics.mean(d["WRITE_SIZE"] for d in _last(_per_dispatch(args.write, _is_accum), args.last))
