@@ -261,21 +261,26 @@ def serve_bench(m, w, rates, seconds=2.0, min_requests=0, warmup_s=None, streams
     return out
 
 
-def make_model(w, data, strategy=1, lane_nnz=2, reg_mode=0, col_order="fixed", prec=None):
+def make_model(w, data, strategy=1, lane_nnz=2, reg_mode=0, col_order="fixed", prec=None,
+               graph=False):
     from paper_1410_5209_amd import tf
     from paper_1410_5209_amd.model import SparseCP
     order_opt = tf.TF_ORDER_RANDOM if col_order == "random" else tf.TF_ORDER_FIXED
     return SparseCP(w.dims, data[0], data[1], w.K, w.lam, precision=prec or w.prec,
-                    strategy=strategy, lane_nnz=lane_nnz, reg_mode=reg_mode, col_order=order_opt)
+                    strategy=strategy, lane_nnz=lane_nnz, reg_mode=reg_mode, col_order=order_opt,
+                    graph=graph)
 
 
-def timed_sweeps(m, C, T_in, steps, warmup, label):
+def timed_sweeps(m, C, T_in, steps, warmup, label, events=True):
+    """`steps` sweeps after `warmup` untimed ones; with `events`, every
+    accumulation launch is also bracketed by HIP events (not possible inside
+    a captured sweep graph)."""
     import torch
     for s in range(warmup):
         m.sweep(C, T_in)
         log(f"{label}: warmup sweep {s} done")
     torch.cuda.synchronize()
-    m.profile(True)
+    m.profile(events)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(steps):
@@ -305,7 +310,8 @@ def run_workload(w, args, steps, warmup, serve=False):
     data = synth.make_tensor(w)
     log(f"{w.name}: generated {data[0].shape[0]} entries in {time.perf_counter() - t0:.1f} s")
     t0 = time.perf_counter()
-    m = make_model(w, data, args.strategy, args.lane_nnz, args.reg_mode, args.col_order)
+    m = make_model(w, data, args.strategy, args.lane_nnz, args.reg_mode, args.col_order,
+                   graph=args.graph)
     torch.cuda.synchronize()
     log(f"{w.name}: tf_init {time.perf_counter() - t0:.1f} s")
     del data
@@ -313,16 +319,19 @@ def run_workload(w, args, steps, warmup, serve=False):
         ([16, 32] if w.name == HEADLINE else [w.C])
     C, tinfo = (w.C, None) if args.no_tune else tune(m, w, cands)
     log(f"{w.name}: C={C}" + (f" (tuned in {tinfo['tune_ms']:.0f} ms)" if tinfo else ""))
-    dt, ks = timed_sweeps(m, C, w.T_in, steps, warmup, w.name)
+    dt, ks = timed_sweeps(m, C, w.T_in, steps, warmup, w.name, events=not args.graph)
     loss, rmse = m.loss()
     ms = dt * 1000.0 / steps
     updates = m.nnz * w.K * w.T_in * w.N
     log(f"{w.name}: timed {steps} sweeps in {dt:.3f} s ({ms:.1f} ms/sweep); loss {loss:.6g} rmse {rmse:.6g}")
     rec = {"workload": w.name, "N": w.N, "dims": w.dims, "nnz": m.nnz, "K": w.K, "C": C,
            "T_in": w.T_in, "lambda": w.lam, "precision": w.prec, "autotune": tinfo,
-           "strategy": args.strategy,
+           "strategy": args.strategy, "graph": bool(args.graph),
            "steps": steps, "warmup": warmup, "ms_per_step": ms, "value": updates / (ms / 1000.0),
-           "roofline": roofline(ks, dt, w.name, C), "loss_after": loss, "train_rmse_after": rmse}
+           "roofline": (roofline(ks, dt, w.name, C) if not args.graph else
+                        {"note": "not measured with --graph: a captured sweep holds no per-kernel "
+                                 "events", "graph_sweeps": ks.graph_sweeps}),
+           "loss_after": loss, "train_rmse_after": rmse}
     serving = None
     if serve and w.N == 3 and w.K <= 128:
         serving = serve_bench(m, w, [1000, 10000, 50000], args.serve_seconds,
@@ -456,6 +465,8 @@ def main():
     ap.add_argument("--strategy", type=int, default=1, choices=[0, 1, 2, 3],
                     help="row plan: 0 plain, 1 skew-aware, 2 skew-aware with tiles timed, 3 persistent")
     ap.add_argument("--lane-nnz", type=int, default=2)
+    ap.add_argument("--graph", action="store_true",
+                    help="sweeps captured as HIP graphs and replayed (tf_options.graph)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", default=None,
                     help="comma-separated candidate C values (default: 16,32 for the 5-way "

@@ -113,6 +113,15 @@ typedef struct tf_options {
     tf_alloc_fn dev_alloc;     /* NULL (default): hipMalloc / hipFree; else */
     tf_free_fn dev_free;       /*   every device allocation of the context */
     void *alloc_user;          /*   goes through these two (both set) */
+    int32_t graph;             /* 1: a tf_sweep whose starting state (C, T_in,
+                                  pending columns, residual placement, row
+                                  plans, buffers) repeats the previous sweep's
+                                  is captured as one HIP graph, and later
+                                  sweeps with that state replay it (one launch
+                                  instead of one per kernel: for tensors small
+                                  enough to be launch-bound).  0 (default):
+                                  every sweep launches its kernels.  Results
+                                  do not depend on it. */
 } tf_options;
 
 /* Residual placement.  Mode 1 keeps R-hat in its own row order and forms it
@@ -401,6 +410,7 @@ typedef struct tf_kstats {
     int64_t first_launches; /* of which first passes of a split (residual */
     double first_ms;        /*   brought up to date in the same walk)     */
     double first_bytes;
+    int64_t graph_sweeps;   /* sweeps captured or replayed as a graph */
 } tf_kstats;
 tf_status tf_profile(tf_ctx *ctx, int32_t enable);        /* 1 on, 0 off; resets */
 tf_status tf_profile_read(tf_ctx *ctx, tf_kstats *out);    /* synchronises */

@@ -253,6 +253,18 @@ __global__ void k_pass_latch(unsigned long long *flags, int nmodes)
     if (any) flags[kStopWord] = 1ull;
 }
 
+// Zero one counter word (a kernel, so that captured sweeps hold no memset).
+__global__ void k_clear_word(unsigned int *p)
+{
+    if (threadIdx.x == 0) p[0] = 0u;
+}
+
+hipError_t launch_clear_word(unsigned int *p, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_clear_word, dim3(1), dim3(64), 0, st, p);
+    return hipGetLastError();
+}
+
 hipError_t launch_pass_latch(unsigned long long *flags, int nmodes, hipStream_t st)
 {
     hipLaunchKernelGGL(k_pass_latch, dim3(1), dim3(64), 0, st, flags, nmodes);

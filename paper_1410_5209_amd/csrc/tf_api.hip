@@ -240,10 +240,10 @@ void fill_accum_args(tf_ctx *c, int n, int npend, AccumArgs *a)
 }
 
 // The work counter of a persistent launch starts at zero (a stream-ordered
-// clear before each launch).
+// clear before each launch, by a kernel: a captured sweep holds no memset).
 tf_status reset_work(tf_ctx *c, const AccumArgs &a)
 {
-    if (a.work) HIPCHK(c, hipMemsetAsync(a.work, 0, sizeof(unsigned int), c->stream));
+    if (a.work) HIPCHK(c, launch_clear_word(a.work, c->stream));
     return TF_OK;
 }
 
@@ -287,14 +287,74 @@ tf_status pack_all(tf_ctx *c, const int32_t *d_cur, int ncur, const int32_t *d_p
 }
 
 // Upload the current columns (offset 0) and the pending columns (offset K).
+// The host side goes through a ring of pinned slots, so a sweep is queued
+// without waiting for the GPU: the copy out of a slot is ordered after the
+// kernels that read the previous list, and a slot is written again only
+// after the stream has drained (when the ring wraps).
+tf_status ensure_ring(tf_ctx *c, int slots)
+{
+    slots = std::max(slots, kColRingSlots);
+    if (c->h_ring && c->ring_slots >= slots) return TF_OK;
+    if (c->h_ring) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        HIPCHK(c, hipHostFree(c->h_ring));
+        c->h_ring = nullptr;
+    }
+    const size_t slot = 2 * (size_t)c->K + 2;
+    HIPCHK(c, hipHostMalloc(reinterpret_cast<void **>(&c->h_ring), (size_t)slots * slot * sizeof(int32_t),
+                            hipHostMallocDefault));
+    c->ring_slots = slots;
+    c->ring_next = 0;
+    return TF_OK;
+}
+
+// Where a column list handed to upload_cols lives, for replays of a
+// captured sweep: a range of the column order, or (see tf_sweep) the
+// sweep's starting pending list.
+tf_ctx::ColSrc col_source(const tf_ctx *c, const int32_t *cols, int ncols)
+{
+    tf_ctx::ColSrc s;
+    if (ncols == 0) return s;
+    const int32_t *o = c->order.data();
+    if (cols >= o && cols + ncols <= o + c->order.size()) {
+        s.kind = 1;
+        s.begin = (int)(cols - o);
+        s.len = ncols;
+    } else {
+        s.kind = -1;   // not reproducible from the order
+    }
+    return s;
+}
+
+void fill_slot(const tf_ctx *c, int32_t *h, const int32_t *cols, int ncols, const int32_t *pend,
+               int npend)
+{
+    std::fill(h, h + 2 * (size_t)c->K + 2, 0);
+    for (int q = 0; q < ncols; ++q) h[q] = cols[q];
+    for (int q = 0; q < npend; ++q) h[c->K + q] = pend[q];
+}
+
 tf_status upload_cols(tf_ctx *c, const int32_t *cols, int ncols)
 {
-    std::vector<int32_t> h(2 * (size_t)c->K + 2, 0);
-    for (int q = 0; q < ncols; ++q) h[q] = cols[q];
-    for (size_t q = 0; q < c->pend.size(); ++q) h[c->K + q] = c->pend[q];
-    HIPCHK(c, hipMemcpyAsync(c->d_cols, h.data(), h.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                             c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));  // h is a stack buffer
+    const size_t slot = 2 * (size_t)c->K + 2;
+    tf_status s = ensure_ring(c, kColRingSlots);
+    if (s != TF_OK) return s;
+    if (c->ring_next == c->ring_slots) {
+        if (c->capturing) {   // no waiting inside a capture: the sweep runs eagerly instead
+            c->capture_bad = true;
+            return CTX_FAIL(c, TF_E_STATE, "column slots exhausted while capturing");
+        }
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->ring_next = 0;
+    }
+    if (c->capturing) {
+        tf_ctx::Upload u{col_source(c, cols, ncols), c->pend_src};
+        if (u.cur.kind < 0 || u.pend.kind < 0) c->capture_bad = true;
+        c->recipe.push_back(u);
+    }
+    int32_t *h = c->h_ring + (size_t)c->ring_next++ * slot;
+    fill_slot(c, h, cols, ncols, c->pend.data(), (int)c->pend.size());
+    HIPCHK(c, hipMemcpyAsync(c->d_cols, h, slot * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
     return TF_OK;
 }
 
@@ -393,6 +453,7 @@ tf_status boundary_on_mode0(tf_ctx *c, const int32_t *d_add, int nadd)
     HIPCHK(c, launch_big_boundary(c->prec, b, c->stream));
     for (int n = 1; n < c->N; ++n) c->m[n].fresh = false;
     c->pend.clear();
+    c->pend_src = tf_ctx::ColSrc{};
     return TF_OK;
 }
 
@@ -468,6 +529,7 @@ tf_status run_split_big(tf_ctx *c, const int32_t *cols, int ncols, int T_in)
         }
     }
     c->pend.assign(cols, cols + ncols);
+    c->pend_src = col_source(c, cols, ncols);
     return TF_OK;
 }
 
@@ -553,6 +615,7 @@ tf_status run_split(tf_ctx *c, const int32_t *cols, int ncols, int T_in)
         if (md.shared) md.fresh = false;
     }
     c->pend.assign(cols, cols + ncols);
+    c->pend_src = col_source(c, cols, ncols);
     return TF_OK;
 }
 
@@ -657,6 +720,12 @@ void destroy_ctx(tf_ctx *c)
     }
     dfree(c, c->gram); dfree(c, c->gpart); dfree(c, c->d_cols); dfree(c, c->d_bad);
     dfree(c, c->d_partials); dfree(c, c->d_scalar);
+    if (c->h_ring) {   // no copy may still read it (also on the null stream)
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipHostFree(c->h_ring);
+    }
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     for (auto e : c->ev_free) (void)hipEventDestroy(e);
     for (auto &t : c->ev_pending) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
     delete c;
@@ -820,6 +889,7 @@ void tf_default_options(tf_options *opt)
     opt->dev_alloc = nullptr;
     opt->dev_free = nullptr;
     opt->alloc_user = nullptr;
+    opt->graph = 0;
 }
 
 const char *tf_last_error(const tf_ctx *ctx)
@@ -861,6 +931,7 @@ tf_status tf_init(tf_ctx **out, int32_t N, const int64_t *dims, int64_t nnz, con
         return set_err(&g_init_err, TF_E_INVALID, "dev_alloc and dev_free must be set together");
     if (o.lane_nnz < 0 || o.split_threshold < 0 || o.chunk_nnz < 0)
         return set_err(&g_init_err, TF_E_INVALID, "negative tuning option");
+    if (o.graph != 0 && o.graph != 1) return set_err(&g_init_err, TF_E_INVALID, "bad graph");
     if (o.resid_share < TF_RESID_AUTO || o.resid_share > TF_RESID_SHARED)
         return set_err(&g_init_err, TF_E_INVALID, "bad resid_share");
     if (o.lane_nnz == 0) o.lane_nnz = 2;
@@ -884,6 +955,15 @@ tf_status tf_init(tf_ctx **out, int32_t N, const int64_t *dims, int64_t nnz, con
     c->opt = o;
     c->prec = o.precision;
     c->stream = (hipStream_t)o.stream;
+    if (o.graph && !c->stream) {
+        // graphs are captured on a stream of the context's own (a blocking
+        // stream at the default priority: ordered with the null stream)
+        if (hipStreamCreate(&c->own_stream) != hipSuccess) {
+            delete c;
+            return set_err(&g_init_err, TF_E_DEVICE, "stream creation failed");
+        }
+        c->stream = c->own_stream;
+    }
     c->device = dev;
     c->err.reserve(512);   // messages up to this length are set without allocating
     for (int n = 0; n < N; ++n) c->dims[n] = dims[n];
@@ -963,6 +1043,147 @@ tf_status tf_split(tf_ctx *ctx, int32_t ncols, const int32_t *h_cols, int32_t T_
     return check_bad(ctx);
 }
 
+namespace {
+
+// What a sweep's device work depends on besides device data: the sizes,
+// flags, plans and buffers its host logic reads.  Equal signatures give the
+// same sequence of launches and copies with the same arguments.  (The slab
+// geometry is not part of it: every split sets it from its own widths
+// before using it, whatever a call between sweeps left.)
+std::vector<int64_t> sweep_signature(const tf_ctx *c, int C, int T_in)
+{
+    auto p = [](const void *q) { return (int64_t)reinterpret_cast<uintptr_t>(q); };
+    std::vector<int64_t> v = {C, T_in, (int64_t)c->pend.size(), c->prec, c->K, c->N, c->slab_cp,
+                              c->gpart_chunks, p(c->gram), p(c->gpart), p(c->d_cols),
+                              p(c->h_ring), c->ring_slots, p(c->d_bad), p(c->stream),
+                              c->opt.strategy, c->opt.reg_mode, c->opt.resid_share};
+    for (int n = 0; n < c->N; ++n) {
+        const auto &md = c->m[n];
+        v.insert(v.end(), {md.shared, md.fresh, md.persistent, md.ntasks, p(md.tasks), p(md.items),
+                           p(md.chunks), md.nsplit, p(md.split_rows), p(md.split_chunk_ptr),
+                           p(md.pos0), p(md.Z), p(md.rhat), p(md.A), md.lane_nnz, md.split_threshold,
+                           md.chunk_nnz});
+    }
+    return v;
+}
+
+void save_flags(const tf_ctx *c, std::vector<char> *f)
+{
+    f->clear();
+    for (int n = 0; n < c->N; ++n) {
+        f->push_back(c->m[n].shared ? 1 : 0);
+        f->push_back(c->m[n].fresh ? 1 : 0);
+    }
+}
+
+void load_flags(tf_ctx *c, const std::vector<char> &f)
+{
+    for (int n = 0; n < c->N; ++n) {
+        c->m[n].shared = f[2 * n] != 0;
+        c->m[n].fresh = f[2 * n + 1] != 0;
+    }
+}
+
+const int32_t *src_ptr(const tf_ctx *c, const tf_ctx::ColSrc &s, const std::vector<int32_t> &start)
+{
+    return s.kind == 1 ? c->order.data() + s.begin : s.kind == 2 ? start.data() + s.begin : nullptr;
+}
+
+tf_status eager_splits(tf_ctx *c, int C, int T_in)
+{
+    for (int b = 0; b < c->K; b += C) {
+        const int w = std::min(C, c->K - b);
+        tf_status s = run_split(c, c->order.data() + b, w, T_in);
+        if (s != TF_OK) return s;
+    }
+    return TF_OK;
+}
+
+// Replay of the captured sweep: its column slots rewritten from the current
+// order and starting pending list, one graph launch, and the host state the
+// captured sweep ended with.
+tf_status replay_sweep(tf_ctx *c)
+{
+    HIPCHK(c, hipStreamSynchronize(c->stream));   // no copy still reads a slot
+    const std::vector<int32_t> start = c->pend;
+    const size_t slot = 2 * (size_t)c->K + 2;
+    for (size_t i = 0; i < c->recipe.size(); ++i) {
+        const auto &u = c->recipe[i];
+        fill_slot(c, c->h_ring + i * slot, src_ptr(c, u.cur, start), u.cur.len,
+                  src_ptr(c, u.pend, start), u.pend.len);
+    }
+    HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
+    const auto &e = c->graph_end_pend;
+    const int32_t *ep = src_ptr(c, e, start);
+    c->pend.assign(ep, ep + e.len);
+    c->pend_src = e;
+    load_flags(c, c->graph_end_flags);
+    c->ld = c->graph_end_ld;
+    c->sw = c->graph_end_sw;
+    c->ring_next = (int)c->recipe.size();
+    return TF_OK;
+}
+
+// The sweep recorded into a graph (nothing runs while recording), then
+// launched.  Returns TF_E_STATE with the host state restored when the
+// sweep could not be captured; the caller then runs it eagerly.
+tf_status capture_sweep(tf_ctx *c, int C, int T_in, const std::vector<int64_t> &sig)
+{
+    HIPCHK(c, hipStreamSynchronize(c->stream));   // every slot is free again
+    const std::vector<int32_t> pend0 = c->pend;
+    const tf_ctx::ColSrc src0 = c->pend_src;
+    std::vector<char> flags0;
+    save_flags(c, &flags0);
+    const int ring0 = c->ring_next;
+    c->ring_next = 0;
+    c->recipe.clear();
+    c->pend_src = tf_ctx::ColSrc{pend0.empty() ? 0 : 2, 0, (int)pend0.size()};
+    c->capture_bad = false;
+    hipGraph_t g = nullptr;
+    std::string why;
+    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    tf_status s = TF_E_STATE;
+    if (e != hipSuccess) {
+        why = std::string("begin: ") + hipGetErrorString(e);
+    } else {
+        c->capturing = true;
+        s = eager_splits(c, C, T_in);
+        c->capturing = false;
+        if (s != TF_OK) why = "recording: " + c->err;
+        e = hipStreamEndCapture(c->stream, &g);
+        if (e != hipSuccess && why.empty()) why = std::string("end: ") + hipGetErrorString(e);
+    }
+    if (why.empty() && c->capture_bad) why = "a column list not taken from the order";
+    hipGraphExec_t x = nullptr;
+    if (why.empty() && g) {
+        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) why = std::string("instantiate: ") + hipGetErrorString(e);
+    }
+    if (g) (void)hipGraphDestroy(g);
+    if (!why.empty() || !x) {
+        if (x) (void)hipGraphExecDestroy(x);
+        (void)hipGetLastError();
+        c->pend = pend0;
+        c->pend_src = src0;
+        load_flags(c, flags0);
+        c->ring_next = ring0;
+        // kept for tf_last_error: the sweep itself then runs eagerly
+        c->err = "sweep graph not captured (" + why + "); the sweep ran without it";
+        return TF_E_STATE;
+    }
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    c->graph_exec = x;
+    c->graph_sig = sig;
+    c->graph_end_pend = c->pend_src;
+    save_flags(c, &c->graph_end_flags);
+    c->graph_end_ld = c->ld;
+    c->graph_end_sw = c->sw;
+    HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
+    return TF_OK;
+}
+
+}  // namespace
+
 tf_status tf_sweep(tf_ctx *ctx, int32_t C, int32_t T_in)
 {
     if (!ctx) return TF_E_INVALID;
@@ -978,11 +1199,28 @@ tf_status tf_sweep(tf_ctx *ctx, int32_t C, int32_t T_in)
     if ((s = reset_bad(ctx)) != TF_OK) return s;
     if (ctx->opt.col_order == TF_ORDER_RANDOM) draw_col_order(ctx->opt.seed, ctx->sweeps_run, ctx->K, ctx->order);
     ctx->sweeps_run += 1;
-    for (int b = 0; b < ctx->K; b += C) {
-        const int w = std::min(C, ctx->K - b);
-        if ((s = run_split(ctx, ctx->order.data() + b, w, T_in)) != TF_OK) return s;
+    // A graph holds the narrow and 32-column paths (no workgroup-per-row
+    // splits, no profiling events); it is recorded the second time a
+    // starting state is seen, when every lazy allocation has been made.
+    const int nsplit = (ctx->K + C - 1) / C;
+    bool graphed = false;
+    if (ctx->opt.graph && !ctx->profiling &&
+        pick_cp(std::max<int>(C, (int)ctx->pend.size()), ctx->prec) > 0) {
+        if ((s = ensure_ring(ctx, 2 * nsplit + 2)) != TF_OK) return s;
+        const std::vector<int64_t> sig = sweep_signature(ctx, C, T_in);
+        if (ctx->graph_exec && sig == ctx->graph_sig) {
+            if ((s = replay_sweep(ctx)) != TF_OK) return s;
+            graphed = true;
+        } else if (sig == ctx->last_sig) {
+            s = capture_sweep(ctx, C, T_in, sig);
+            if (s == TF_OK) graphed = true;
+            else if (s != TF_E_STATE) return s;
+        }
+        ctx->last_sig = sig;
     }
+    if (!graphed && (s = eager_splits(ctx, C, T_in)) != TF_OK) return s;
     ctx->kstats.sweeps += 1;
+    if (graphed) ctx->kstats.graph_sweeps += 1;
     return check_bad(ctx);
 }
 

@@ -81,6 +81,7 @@ struct SolveArgs {
 // Workgroup-per-row path for splits wider than the register and wide kernels
 // take (k_big.hip), up to kMaxBigC columns.
 constexpr int kMaxBigC = 128;
+constexpr int kColRingSlots = 64;   // pinned staging slots for split column lists (at least)
 struct BigArgs {
     const int32_t *rowptr;               // this mode
     const int32_t *items;                // non-empty rows that are not chunked
@@ -128,6 +129,7 @@ int64_t big_record_stride(int C);
 hipError_t launch_accum(int prec, int CP, int no, bool first, const AccumArgs &a, int grid,
                         hipStream_t st);
 hipError_t launch_solve(int prec, int CP, const SolveArgs &a, hipStream_t st);
+hipError_t launch_clear_word(unsigned int *p, hipStream_t st);
 hipError_t launch_pass_latch(unsigned long long *flags, int nmodes, hipStream_t st);
 hipError_t launch_chunk_reduce(int prec, int CP, const int32_t *split_rows,
                                const int32_t *split_chunk_ptr, int nsplit, const void *gpart,
@@ -253,6 +255,9 @@ struct tf_ctx {
     void *gpart = nullptr;    // max_chunks x gram_stride(slab_cp) (TA)
     size_t gpart_bytes = 0;   // its size
     int32_t *d_cols = nullptr;  // device copy of split columns + pending columns
+    int32_t *h_ring = nullptr;  // pinned staging slots for d_cols (ring_slots x (2K + 2))
+    int ring_slots = 0;
+    int ring_next = 0;
     unsigned long long *d_bad = nullptr;  // kFlagWords failure flags (pass_halted)
     double *d_partials = nullptr;
     int64_t partials_cap = 0;
@@ -270,6 +275,23 @@ struct tf_ctx {
     tf_kstats kstats{};
     int64_t sweeps_run = 0;         // tf_sweep calls (keys the random column orders)
     int auto_cp = 0;                // TF_STRATEGY_AUTO: width the tiles were tuned for
+
+    // A sweep as one HIP graph (opt.graph).  Its device work depends on the
+    // host state at its start only through the sizes, flags and buffers in
+    // sweep_signature; the column lists it copies are rebuilt in their
+    // pinned slots before each replay from where they came from: a range of
+    // the column order, or the sweep's starting pending list.
+    struct ColSrc { int kind = 0, begin = 0, len = 0; };   // 0 none, 1 order, 2 starting pend
+    struct Upload { ColSrc cur, pend; };
+    ColSrc pend_src;                // where pend came from (kept while capturing)
+    bool capturing = false, capture_bad = false;
+    std::vector<Upload> recipe;     // the captured sweep's column uploads, one per slot
+    std::vector<int64_t> graph_sig, last_sig;
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t own_stream = nullptr;   // created when a graph is asked for without a stream
+    ColSrc graph_end_pend;          // pend after the captured sweep
+    std::vector<char> graph_end_flags;  // shared, fresh per mode after it
+    int64_t graph_end_ld = 0, graph_end_sw = 0;   // slab geometry after it
 
     // device memory of the context (ctx_alloc / ctx_free): the caller's hooks
     // or hipMalloc, counted against opt.mem_budget

@@ -13,7 +13,7 @@ class SparseCP:
     def __init__(self, dims, idx, vals, K, lam, precision="f32", reg_mode=0,
                  first_factor_zero=True, strategy=tf.TF_STRATEGY_SKEW, seed=2, stream=None,
                  lane_nnz=2, split_threshold=4096, chunk_nnz=2048, resid_share=tf.TF_RESID_AUTO,
-                 col_order=tf.TF_ORDER_FIXED, mem_budget=0, torch_alloc=False):
+                 col_order=tf.TF_ORDER_FIXED, mem_budget=0, torch_alloc=False, graph=False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("SparseCP needs a HIP GPU")
@@ -35,7 +35,8 @@ class SparseCP:
                                     strategy=int(strategy), seed=int(seed), stream=stream,
                                     lane_nnz=int(lane_nnz), split_threshold=int(split_threshold),
                                     chunk_nnz=int(chunk_nnz), resid_share=int(resid_share),
-                                    col_order=int(col_order), mem_budget=int(mem_budget))
+                                    col_order=int(col_order), mem_budget=int(mem_budget),
+                                    graph=1 if graph else 0)
         if torch_alloc:
             # the library's device memory comes from torch's caching allocator
             dev_index = torch.cuda.current_device()

@@ -35,14 +35,14 @@ class tf_options(ctypes.Structure):
                 ("split_threshold", ctypes.c_int32), ("chunk_nnz", ctypes.c_int32),
                 ("resid_share", ctypes.c_int32), ("col_order", ctypes.c_int32),
                 ("mem_budget", ctypes.c_size_t), ("dev_alloc", ALLOC_FN),
-                ("dev_free", FREE_FN), ("alloc_user", ctypes.c_void_p)]
+                ("dev_free", FREE_FN), ("alloc_user", ctypes.c_void_p), ("graph", ctypes.c_int32)]
 
 
 class tf_kstats(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
                 ("alg_bytes", ctypes.c_double), ("sweeps", ctypes.c_int64),
                 ("first_launches", ctypes.c_int64), ("first_ms", ctypes.c_double),
-                ("first_bytes", ctypes.c_double)]
+                ("first_bytes", ctypes.c_double), ("graph_sweeps", ctypes.c_int64)]
 
 
 class tf_plan_summary(ctypes.Structure):

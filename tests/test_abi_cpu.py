@@ -19,12 +19,13 @@ def test_library_exports_every_declared_symbol():
 
 def test_options_struct_matches_header_defaults():
     o = tf.tf_default_options()
-    assert o.size == ctypes.sizeof(tf.tf_options) == 96
+    assert o.size == ctypes.sizeof(tf.tf_options) == 104
     assert (o.precision, o.reg_mode, o.first_factor_zero, o.strategy, o.seed) == (1, 0, 1, 1, 2)
     assert (o.lane_nnz, o.split_threshold, o.chunk_nnz) == (2, 4096, 2048)
     assert o.resid_share == tf.TF_RESID_AUTO
     assert o.col_order == tf.TF_ORDER_FIXED and o.mem_budget == 0
     assert not o.dev_alloc and not o.dev_free and o.alloc_user is None
+    assert o.graph == 0
 
 
 def _rowptr(counts):
@@ -77,7 +78,8 @@ def test_init_rejects_bad_arguments_on_host():
         assert ctx.value is None
         assert len(tf.tf_last_error(None)) > 0
     bad_opts = [tf.tf_default_options(precision=7), tf.tf_default_options(strategy=4),
-                tf.tf_default_options(col_order=2), tf.tf_default_options(resid_share=5)]
+                tf.tf_default_options(col_order=2), tf.tf_default_options(resid_share=5),
+                tf.tf_default_options(graph=2)]
     half = tf.tf_default_options()
     half.dev_alloc = tf.ALLOC_FN(lambda n, s, u: None)   # dev_free left NULL
     bad_opts.append(half)

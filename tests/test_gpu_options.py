@@ -108,3 +108,42 @@ def test_persistent_launch_gives_the_skew_results_bit_for_bit(C):
     for a, b in zip(runs[0][0], runs[1][0]):
         assert np.array_equal(a, b)
     assert np.array_equal(runs[0][1], runs[1][1])
+
+
+GRAPH_CASES = {
+    # precision, dims, nnz, K, C per sweep, T_in, options
+    "f64-cdtf": ("f64", [300, 200, 100], 20000, 10, [1] * 5, 1, {}),
+    "f32-random-order": ("f32", [400, 300, 200], 30000, 20,
+                         [4, 4, 4, 4, 3, 3, 3, 3, 4, 4, 4], 2, {"col_order": 1}),
+    "f32-wide-persistent": ("f32", [300, 250, 200, 150], 30000, 40, [32] * 5, 1,
+                            {"strategy": 3}),
+    "bf16-shared": ("bf16", [400, 300, 200], 30000, 40, [16] * 5, 2, {"resid_share": 2}),
+}
+
+
+@pytest.mark.parametrize("case", sorted(GRAPH_CASES))
+def test_sweep_graph_replays_equal_eager_sweeps_bit_for_bit(case):
+    """tf_options.graph: a sweep whose starting state repeats the previous
+    sweep's is captured as one HIP graph, and later sweeps with that state
+    replay it.  After every sweep (loss, factors and residual read eagerly
+    between the replays), factors, residual and loss equal those of a
+    context that launches every kernel, bit for bit, also when C changes (a
+    new capture) and changes back, with a random column order per sweep."""
+    prec, dims, nnz, K, Cs, T_in, opts = GRAPH_CASES[case]
+    note(f"sweep graph {case}")
+    idx, x, A = problem(390 + len(dims) + K, dims, nnz, K, dist="zipf", dedupe="drop")
+    ge, _ = pair(dims, idx, x, A, K, 0.5, prec, split_threshold=512, chunk_nnz=128, **opts)
+    gg, _ = pair(dims, idx, x, A, K, 0.5, prec, split_threshold=512, chunk_nnz=128, graph=True,
+                 **opts)
+    for s, C in enumerate(Cs):
+        ge.sweep(C, T_in)
+        gg.sweep(C, T_in)
+        for n in range(len(dims)):
+            assert np.array_equal(ge.factor(n), gg.factor(n)), (s, n)
+        assert np.array_equal(ge.residual(), gg.residual()), s
+        assert ge.loss() == gg.loss(), s
+    # the graph path was taken (captured, then replayed) for the repeated states
+    assert gg.profile_read().graph_sweeps >= 2
+    assert ge.profile_read().graph_sweeps == 0
+    ge.close()
+    gg.close()
