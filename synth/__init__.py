@@ -193,6 +193,9 @@ WORKLOADS = {
     # SALS, FP32, 5-way 1M^5, 5e8 Zipf(1.0) draws, K = 1000 (scaled S4 shape)
     "sals-5way-zipf-fp32": Workload("sals-5way-zipf-fp32", 5, 1_000_000, 500_000_000, "zipf", 1.0,
                                     "drop", 20, 0, 0.25, 1000, 1.0, 20, 1, 1, "f32"),
+    # the 5-way workload with BF16 factor storage (FP32 arithmetic)
+    "sals-5way-zipf-bf16": Workload("sals-5way-zipf-bf16", 5, 1_000_000, 500_000_000, "zipf", 1.0,
+                                    "drop", 20, 0, 0.25, 1000, 1.0, 20, 1, 1, "bf16"),
     # the 3-way SALS workload with BF16 factors and a 1% held-out test split
     "sals-3way-1m-bf16": Workload("sals-3way-1m-bf16", 3, 1_000_000, 100_000_000, "uniform", 0.0,
                                   "distinct", 20, 1, 0.25, 100, 1.0, 10, 2, 10, "bf16", 0.01),
