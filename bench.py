@@ -188,8 +188,9 @@ def roofline(ks, dt_s, workload, C):
            "kernel_share_of_sweep": ks.total_ms / (dt_s * 1000.0),
            "alg_bytes_per_launch": alg_bpl, "alg_achieved": alg_gbs,
            "alg_frac": alg_gbs / HBM_PEAK_GBS,
-           "note": ("achieved = HBM-side bytes per launch (rocprofv3 TCC read and write requests by "
-                    "size, committed summary of this kernel source: lines that miss L2, so they "
+           "note": ("achieved = HBM-side bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, each "
+                    "scaled by its reading for a 1 GiB copy; the L2's requests counted by size "
+                    "agree; committed summary of this kernel source: lines that miss L2, so they "
                     "include the 256 MB last-level cache's hits) / average launch time measured "
                     "here; alg_* = design-neutral algorithmic bytes (every gathered factor row, "
                     "index and residual counted at its size each use, no cache credit) / the same "
@@ -197,12 +198,14 @@ def roofline(ks, dt_s, workload, C):
     if t is None:
         out["note"] += "; counter summary missing or from another kernel source: achieved unknown"
         return out
-    bpl = t["bytes_per_launch"]
+    # FETCH_SIZE + WRITE_SIZE per launch, each scaled by its reading for a
+    # 1 GiB device copy; the L2's requests counted by size agree with it
+    bpl = t.get("fetch_size_bytes_per_launch") or t["bytes_per_launch"]
     gbs = bpl / 1e9 / (avg_ms / 1e3)
     out.update({"achieved": gbs, "frac": gbs / HBM_PEAK_GBS, "traffic": bpl,
+                "traffic_requests_by_size": t.get("bytes_per_launch"),
                 "traffic_read": t.get("read_bytes_per_launch"),
                 "traffic_write": t.get("write_bytes_per_launch"),
-                "traffic_fetch_size_calibrated": t.get("fetch_size_bytes_per_launch"),
                 "traffic_dram_destined": t.get("dram_destined_bytes_per_launch"),
                 "l2_hit_rate": t.get("hit_rate")})
     ceil = _profile_json("gather_ceiling.json")
