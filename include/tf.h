@@ -121,7 +121,9 @@ typedef struct tf_options {
                                   instead of one per kernel: for tensors small
                                   enough to be launch-bound).  0 (default):
                                   every sweep launches its kernels.  Results
-                                  do not depend on it. */
+                                  do not depend on it.  A sweep that cannot be
+                                  captured runs without a graph, and
+                                  tf_last_error then says why. */
 } tf_options;
 
 /* Residual placement.  Mode 1 keeps R-hat in its own row order and forms it
