@@ -301,6 +301,10 @@ def main():
                   f"accumulation kernels: average launch {rf['avg_launch_ms']:.3f} ms (HIP events), "
                   f"{rf['alg_bytes_per_launch']/1e9:.3f} GB algorithmic per launch "
                   f"({rf['alg_achieved']:.0f} GB/s, {100*rf['alg_frac']:.1f}% of 8 TB/s without cache credit)."]
+        if rf.get("achieved"):
+            lines += ["", f"Its bounded roofline: {rf['achieved']:.0f} GB/s of HBM-side traffic, frac "
+                      f"{rf['frac']:.3f}; L2-miss lines at {rf['l2_miss_line_rate']['achieved_glines_s']:.1f} "
+                      f"G/s, {rf['l2_miss_line_rate'].get('frac', 0):.2f} of the gather ceiling."]
     out = os.path.join(ROOT, "profiles", f"k_accum_{args.workload}.md")
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
