@@ -139,11 +139,170 @@ __device__ __forceinline__ void sum_chunk_records(const FoldArgs &a, int q, doub
     const int64_t gs = fold_gram_stride(K);
     const int c0 = a.chunk_first[q], nc = a.chunk_first[q + 1] - c0;
     const TA *gp = reinterpret_cast<const TA *>(a.gpart) + (int64_t)c0 * gs;
-    for (int e = threadIdx.x; e < KT + K; e += blockDim.x) {
-        double sum = 0.0;
-        for (int t = 0; t < nc; ++t) sum += (double)gp[(int64_t)t * gs + e];
-        if (e < KT) L[e] = sum;
-        else rhs[e - KT] = sum;
+    // U elements per thread and 4 chunks at a time in flight; each element
+    // is still summed over the chunks in chunk order
+    constexpr int U = 4;
+    const int nb = blockDim.x;
+    for (int e0 = threadIdx.x; e0 < KT + K; e0 += U * nb) {
+        double sum[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) { sum[u] = 0.0; ok[u] = e0 + u * nb < KT + K; }
+        int t = 0;
+        for (; t + 4 <= nc; t += 4) {
+            TA v[4][U];
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    v[tt][u] = ok[u] ? gp[(int64_t)(t + tt) * gs + e0 + u * nb] : TA(0);
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+                for (int u = 0; u < U; ++u) sum[u] += (double)v[tt][u];
+        }
+        for (; t < nc; ++t)
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (ok[u]) sum[u] += (double)gp[(int64_t)t * gs + e0 + u * nb];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * nb;
+            if (!ok[u]) continue;
+            if (e < KT) L[e] = sum[u];
+            else rhs[e - KT] = sum[u];
+        }
+    }
+}
+
+// Packed lower triangle: element (i, k), k <= i.
+__device__ __forceinline__ int tri(int i, int k) { return i * (i + 1) / 2 + k; }
+
+// A double held by lane j, to every lane of the wavefront.
+__device__ __forceinline__ double lane_bcast(double v, int j)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), j);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), j);
+    return __hiloint2double(hi, lo);
+}
+
+constexpr int kPanel = 32;   // columns per panel of the blocked Cholesky
+
+// Cholesky of the diagonal block (rows and columns c0 .. c0 + w - 1, w <=
+// 32) of the packed triangle, in place, by one wavefront: lane i holds row i
+// of the block in registers.  Step j: lane j's pivot reaches every lane by
+// lane reads; lanes i > j form L(i, j) and publish it in col[]; every lane
+// updates its row from there (LDS accesses of one wavefront stay in program
+// order).  rdiag[c0 + j] = 1 / L(j, j).  A non-positive pivot sets *failed
+// and the factorisation goes on with 1 (the request is then reported).
+__device__ __forceinline__ void fold_diag_block(double *L, int c0, int w, double *rdiag, double *col, int *failed)
+{
+    const int i = threadIdx.x & 63;
+    const bool in = i < w;
+    double m[kPanel];
+#pragma unroll
+    for (int k = 0; k < kPanel; ++k) m[k] = (in && k <= i) ? L[tri(c0 + i, c0 + k)] : 0.0;
+#pragma unroll
+    for (int j = 0; j < kPanel; ++j) {
+        if (j >= w) continue;   // (not break: the loop must unroll fully)
+        const double d = lane_bcast(m[j], j);
+        const bool ok = d > 0.0;
+        const double ljj = sqrt(ok ? d : 1.0), rinv = 1.0 / ljj;
+        if (i == 0 && !ok) *failed = 1;
+        double lij = 0.0;
+        if (in && i > j) {
+            lij = m[j] * rinv;
+            m[j] = lij;
+            col[i] = lij;
+        }
+        if (i == j) {
+            m[j] = ljj;
+            rdiag[c0 + j] = rinv;
+        }
+        __builtin_amdgcn_wave_barrier();
+        asm volatile("" ::: "memory");
+        // M(i, k) -= L(i, j) L(k, j) for k > j (lanes with no row, or k
+        // beyond their row, update scratch registers that are not stored)
+#pragma unroll
+        for (int k0 = j + 1; k0 < kPanel; k0 += 8) {
+            double c[8];
+#pragma unroll
+            for (int k = k0; k < k0 + 8 && k < kPanel; ++k) c[k - k0] = col[k];
+#pragma unroll
+            for (int k = k0; k < k0 + 8 && k < kPanel; ++k) {
+                m[k] -= lij * c[k - k0];
+                asm volatile("" : "+v"(m[k]));
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        asm volatile("" ::: "memory");
+    }
+#pragma unroll
+    for (int k = 0; k < kPanel; ++k)
+        if (in && k <= i) L[tri(c0 + i, c0 + k)] = m[k];
+}
+
+// Rows below the diagonal block: L(r, c0..) = A(r, c0..) L11^{-T}, one
+// thread per row, forward substitution against the block.
+__device__ __forceinline__ void fold_panel_rows(double *L, int c0, int w, int K, const double *rdiag)
+{
+    for (int r = c0 + w + (int)threadIdx.x; r < K; r += blockDim.x) {
+        const int base = tri(r, c0);
+        double x[kPanel];
+#pragma unroll
+        for (int k = 0; k < kPanel; ++k) x[k] = k < w ? L[base + k] : 0.0;
+#pragma unroll
+        for (int k = 0; k < kPanel; ++k) {
+            if (k >= w) continue;
+            double s = x[k];
+            const int bk = tri(c0 + k, c0);
+#pragma unroll
+            for (int t = 0; t < k; ++t) s -= x[t] * L[bk + t];
+            x[k] = s * rdiag[c0 + k];
+        }
+#pragma unroll
+        for (int k = 0; k < kPanel; ++k)
+            if (k < w) L[base + k] = x[k];
+    }
+}
+
+// Trailing update of the rows and columns after the panel, in 4 x 4 tiles
+// of the lower triangle: A(r, s) -= sum_k L(r, k) L(s, k) over the panel.
+__device__ __forceinline__ void fold_trailing(double *L, int c0, int w, int K)
+{
+    const int c1 = c0 + w, n = K - c1;
+    if (n <= 0) return;
+    const int T = (n + 3) / 4, ntile = T * (T + 1) / 2;
+    for (int t = threadIdx.x; t < ntile; t += blockDim.x) {
+        int ti = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+        while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+        while (ti * (ti + 1) / 2 > t) --ti;
+        const int tj = t - ti * (ti + 1) / 2;
+        const int r0 = c1 + 4 * ti, s0 = c1 + 4 * tj;
+        double acc[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+        for (int k = 0; k < w; ++k) {
+            double ra[4], sb[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                ra[u] = r0 + u < K ? L[tri(r0 + u, c0 + k)] : 0.0;
+                sb[u] = s0 + u < K ? L[tri(s0 + u, c0 + k)] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] += ra[u] * sb[v];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = r0 + u, c = s0 + v;
+                if (r < K && c <= r) L[tri(r, c)] -= acc[u][v];
+            }
     }
 }
 
@@ -174,69 +333,77 @@ __global__ __launch_bounds__(256) void k_fold_full(FoldArgs a)
     for (int k = tid; k < K; k += 256) L[k * (k + 1) / 2 + k] += lam;
     __syncthreads();
 
-    // Cholesky L L^T of the packed lower triangle (text after Theorem 1).
-    // Each thread owns fixed positions p = tid + 256 t of the triangle, their
-    // (row, column) decoded once; step j scales column j and updates the
-    // owned elements right of it.  The diagonal of L goes to diag[].
-    constexpr int kOwn = (kFoldMaxKFull * (kFoldMaxKFull + 1) / 2 + 255) / 256;
-    __shared__ double diag[kFoldMaxKFull];
+    // Cholesky L L^T of the packed lower triangle (text after Theorem 1),
+    // right-looking in panels of 32 columns: the panel's diagonal block by
+    // one wavefront, the rows below it one per thread, then the trailing
+    // lower triangle in 4 x 4 tiles (three workgroup barriers per panel).
+    __shared__ double rdiag[kFoldMaxKFull];
+    __shared__ double col[kPanel];
     __shared__ int failed;
-    const int KT = K * (K + 1) / 2;
-    int own[kOwn];
-#pragma unroll
-    for (int t = 0; t < kOwn; ++t) {
-        const int p = tid + 256 * t;
-        own[t] = -1;
-        if (p < KT) {
-            int r = (int)((sqrtf(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
-            while ((r + 1) * (r + 2) / 2 <= p) ++r;
-            while (r * (r + 1) / 2 > p) --r;
-            own[t] = (r << 8) | (p - r * (r + 1) / 2);
-        }
-    }
+    const int wave = tid >> 6, lane = tid & 63;
     if (tid == 0) failed = 0;
-    for (int j = 0; j < K; ++j) {
-        __syncthreads();
-        const double d = L[j * (j + 1) / 2 + j];
-        const double ljj = sqrt(d > 0.0 ? d : 1.0), rinv = 1.0 / ljj;
-        if (tid == 0) {
-            diag[j] = ljj;
-            if (!(d > 0.0)) failed = 1;
-        }
-        for (int i = j + 1 + tid; i < K; i += 256) L[i * (i + 1) / 2 + j] *= rinv;
-        __syncthreads();
-#pragma unroll
-        for (int t = 0; t < kOwn; ++t) {
-            const int i = own[t] >> 8, k = own[t] & 255;
-            if (own[t] >= 0 && k > j)
-                L[i * (i + 1) / 2 + k] -= L[i * (i + 1) / 2 + j] * L[k * (k + 1) / 2 + j];
-        }
-    }
     __syncthreads();
+    for (int c0 = 0; c0 < K; c0 += kPanel) {
+        const int w = K - c0 < kPanel ? K - c0 : kPanel;
+        if (wave == 0) fold_diag_block(L, c0, w, rdiag, col, &failed);
+        __syncthreads();
+        fold_panel_rows(L, c0, w, K, rdiag);
+        __syncthreads();
+        fold_trailing(L, c0, w, K);
+        __syncthreads();
+    }
     if (tid == 0 && a.req_status) a.req_status[q] = failed ? TF_E_NUMERIC : TF_OK;
     if (failed) {
         if (tid == 0) atomicMin(a.bad_req, (unsigned long long)q);
         for (int k = tid; k < K; k += 256) out[k] = 0.0;
         return;
     }
-    // L y = rhs, then L^T a = y, by one wavefront (its LDS accesses stay in
-    // program order, so no barriers)
-    if (tid >= 64) return;
-    for (int k = 0; k < K; ++k) {
-        const double yk = rhs[k] / diag[k];
-        __builtin_amdgcn_wave_barrier();
-        for (int i = k + 1 + tid; i < K; i += 64) rhs[i] -= L[i * (i + 1) / 2 + k] * yk;
-        if (tid == 0) rhs[k] = yk;
-        __builtin_amdgcn_wave_barrier();
+    // L y = c, then L^T a = y, panel by panel: each panel's diagonal block by
+    // one wavefront (lane i holds its unknown; the solved value reaches the
+    // lanes by lane reads), the other rows updated one per thread.
+    for (int c0 = 0; c0 < K; c0 += kPanel) {
+        const int w = K - c0 < kPanel ? K - c0 : kPanel;
+        if (wave == 0) {
+            double y = lane < w ? rhs[c0 + lane] : 0.0;
+#pragma unroll
+            for (int j = 0; j < kPanel; ++j) {
+                if (j >= w) continue;
+                const double yj = lane_bcast(y, j) * rdiag[c0 + j];
+                if (lane == j) y = yj;
+                if (lane > j && lane < w) y -= L[tri(c0 + lane, c0 + j)] * yj;
+            }
+            if (lane < w) rhs[c0 + lane] = y;
+        }
+        __syncthreads();
+        for (int r = c0 + w + tid; r < K; r += 256) {
+            double s = 0.0;
+            for (int k = 0; k < w; ++k) s += L[tri(r, c0 + k)] * rhs[c0 + k];
+            rhs[r] -= s;
+        }
+        __syncthreads();
     }
-    for (int k = K - 1; k >= 0; --k) {
-        const double ak = rhs[k] / diag[k];
-        __builtin_amdgcn_wave_barrier();
-        for (int i = tid; i < k; i += 64) rhs[i] -= L[k * (k + 1) / 2 + i] * ak;
-        if (tid == 0) rhs[k] = ak;
-        __builtin_amdgcn_wave_barrier();
+    for (int c0 = (K - 1) / kPanel * kPanel; c0 >= 0; c0 -= kPanel) {
+        const int w = K - c0 < kPanel ? K - c0 : kPanel;
+        if (wave == 0) {
+            double y = lane < w ? rhs[c0 + lane] : 0.0;
+#pragma unroll
+            for (int j = kPanel - 1; j >= 0; --j) {
+                if (j >= w) continue;
+                const double aj = lane_bcast(y, j) * rdiag[c0 + j];
+                if (lane == j) y = aj;
+                if (lane < j) y -= L[tri(c0 + j, c0 + lane)] * aj;
+            }
+            if (lane < w) rhs[c0 + lane] = y;
+        }
+        __syncthreads();
+        for (int r = tid; r < c0; r += 256) {
+            double s = 0.0;
+            for (int k = 0; k < w; ++k) s += L[tri(c0 + k, r)] * rhs[c0 + k];
+            rhs[r] -= s;
+        }
+        __syncthreads();
     }
-    for (int k = tid; k < K; k += 64) out[k] = rhs[k];
+    for (int k = tid; k < K; k += 256) out[k] = rhs[k];
 }
 
 // CDTF fold-in of one request per workgroup: a = 0, then `sweeps` passes
