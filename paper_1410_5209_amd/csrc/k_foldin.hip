@@ -186,6 +186,17 @@ __device__ __forceinline__ double lane_bcast(double v, int j)
     return __hiloint2double(hi, lo);
 }
 
+// Sum over the wavefront, the same in every lane, in a fixed order: DPP
+// steps within each row of 16 lanes, then the four row sums by lane reads.
+__device__ __forceinline__ double wave_sum(double v)
+{
+    v += dpp_mov<0xB1>(v);    // quad_perm 1,0,3,2
+    v += dpp_mov<0x4E>(v);    // quad_perm 2,3,0,1
+    v += dpp_mov<0x141>(v);   // row_half_mirror
+    v += dpp_mov<0x140>(v);   // row_mirror
+    return (lane_bcast(v, 0) + lane_bcast(v, 16)) + (lane_bcast(v, 32) + lane_bcast(v, 48));
+}
+
 constexpr int kPanel = 32;   // columns per panel of the blocked Cholesky
 
 // Cholesky of the diagonal block (rows and columns c0 .. c0 + w - 1, w <=
@@ -440,11 +451,11 @@ __global__ __launch_bounds__(256) void k_fold_cdtf(FoldArgs a)
     auto bidx = [](int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; };
     for (int s = 0; s < a.sweeps; ++s) {
         for (int k = 0; k < K; ++k) {
-            // sum over k' != k of B_kk' a_k' (fixed tree over the wavefront)
+            // sum over k' != k of B_kk' a_k' (fixed order over the wavefront)
             double t = 0.0;
             if (l0 < K && l0 != k) t += B[bidx(k, l0)] * a0;
             if (l1 < K && l1 != k) t += B[bidx(k, l1)] * a1;
-            for (int sh = 32; sh >= 1; sh >>= 1) t += __shfl_xor(t, sh, 64);
+            t = wave_sum(t);
             const double bkk = B[k * (k + 1) / 2 + k];
             const double ak = (c[k] - t) / (lam + bkk);
             if (l0 == k) a0 = ak;
