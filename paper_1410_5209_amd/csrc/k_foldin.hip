@@ -131,6 +131,49 @@ __global__ __launch_bounds__(256) void k_fold_gram(FoldArgs a)
 
 // B (packed lower triangle) and c of request q in FP64: its chunk records
 // summed in chunk order (every thread of the block takes part).
+// Elements e0 + u * nb (u < U) of a request's nc chunk records, each summed
+// over the chunks in chunk order, CT chunks at a time.  The loads are not
+// conditional (indices past the ends are clamped and their values dropped),
+// so a group of them is issued together.
+template <typename TA, int CT>
+__device__ __forceinline__ void sum_records_group(const TA *gp, int64_t gs, int nc, int e0, int nb,
+                                                  int total, int KT, double *L, double *rhs)
+{
+    constexpr int U = 4;
+    double sum[U];
+    int eu[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        sum[u] = 0.0;
+        const int e = e0 + u * nb;
+        eu[u] = e < total ? e : total - 1;
+    }
+    for (int t0 = 0; t0 < nc; t0 += CT) {
+        TA v[CT][U];
+#pragma unroll
+        for (int tt = 0; tt < CT; ++tt) {
+            const int64_t row = (int64_t)(t0 + tt < nc ? t0 + tt : nc - 1) * gs;
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[tt][u] = gp[row + eu[u]];
+        }
+#pragma unroll
+        for (int tt = 0; tt < CT; ++tt)
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (t0 + tt < nc) sum[u] += (double)v[tt][u];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * nb;
+        if (e >= total) continue;
+        if (e < KT) L[e] = sum[u];
+        else rhs[e - KT] = sum[u];
+    }
+}
+
+// A request's Gram record (packed lower triangle of B, then c): the sum of
+// its chunk records in chunk order, in FP64; the chunk group matches the
+// request's size (most requests have one chunk).
 template <typename TA>
 __device__ __forceinline__ void sum_chunk_records(const FoldArgs &a, int q, double *L, double *rhs)
 {
@@ -139,39 +182,11 @@ __device__ __forceinline__ void sum_chunk_records(const FoldArgs &a, int q, doub
     const int64_t gs = fold_gram_stride(K);
     const int c0 = a.chunk_first[q], nc = a.chunk_first[q + 1] - c0;
     const TA *gp = reinterpret_cast<const TA *>(a.gpart) + (int64_t)c0 * gs;
-    // U elements per thread and 4 chunks at a time in flight; each element
-    // is still summed over the chunks in chunk order
-    constexpr int U = 4;
-    const int nb = blockDim.x;
-    for (int e0 = threadIdx.x; e0 < KT + K; e0 += U * nb) {
-        double sum[U];
-        bool ok[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) { sum[u] = 0.0; ok[u] = e0 + u * nb < KT + K; }
-        int t = 0;
-        for (; t + 4 <= nc; t += 4) {
-            TA v[4][U];
-#pragma unroll
-            for (int tt = 0; tt < 4; ++tt)
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    v[tt][u] = ok[u] ? gp[(int64_t)(t + tt) * gs + e0 + u * nb] : TA(0);
-#pragma unroll
-            for (int tt = 0; tt < 4; ++tt)
-#pragma unroll
-                for (int u = 0; u < U; ++u) sum[u] += (double)v[tt][u];
-        }
-        for (; t < nc; ++t)
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (ok[u]) sum[u] += (double)gp[(int64_t)t * gs + e0 + u * nb];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = e0 + u * nb;
-            if (!ok[u]) continue;
-            if (e < KT) L[e] = sum[u];
-            else rhs[e - KT] = sum[u];
-        }
+    const int nb = blockDim.x, total = KT + K;
+    for (int e0 = threadIdx.x; e0 < total; e0 += 4 * nb) {
+        if (nc == 1) sum_records_group<TA, 1>(gp, gs, nc, e0, nb, total, KT, L, rhs);
+        else if (nc <= 4) sum_records_group<TA, 4>(gp, gs, nc, e0, nb, total, KT, L, rhs);
+        else sum_records_group<TA, 16>(gp, gs, nc, e0, nb, total, KT, L, rhs);
     }
 }
 
@@ -199,6 +214,16 @@ __device__ __forceinline__ double wave_sum(double v)
 
 constexpr int kPanel = 32;   // columns per panel of the blocked Cholesky
 
+// 1 / sqrt(d) for d > 0: the hardware estimate and two steps of Newton's
+// iteration r <- r (3 - d r^2) / 2, each roughly doubling the correct bits.
+__device__ __forceinline__ double fold_rsqrt(double d)
+{
+    double r = __builtin_amdgcn_rsq(d);
+    r = r * (1.5 - 0.5 * d * r * r);
+    r = r * (1.5 - 0.5 * d * r * r);
+    return r;
+}
+
 // Cholesky of the diagonal block (rows and columns c0 .. c0 + w - 1, w <=
 // 32) of the packed triangle, in place, by one wavefront: lane i holds row i
 // of the block in registers.  Step j: lane j's pivot reaches every lane by
@@ -218,7 +243,7 @@ __device__ __forceinline__ void fold_diag_block(double *L, int c0, int w, double
         if (j >= w) continue;   // (not break: the loop must unroll fully)
         const double d = lane_bcast(m[j], j);
         const bool ok = d > 0.0;
-        const double ljj = sqrt(ok ? d : 1.0), rinv = 1.0 / ljj;
+        const double dd = ok ? d : 1.0, rinv = fold_rsqrt(dd), ljj = dd * rinv;
         if (i == 0 && !ok) *failed = 1;
         double lij = 0.0;
         if (in && i > j) {
@@ -235,16 +260,7 @@ __device__ __forceinline__ void fold_diag_block(double *L, int c0, int w, double
         // M(i, k) -= L(i, j) L(k, j) for k > j (lanes with no row, or k
         // beyond their row, update scratch registers that are not stored)
 #pragma unroll
-        for (int k0 = j + 1; k0 < kPanel; k0 += 8) {
-            double c[8];
-#pragma unroll
-            for (int k = k0; k < k0 + 8 && k < kPanel; ++k) c[k - k0] = col[k];
-#pragma unroll
-            for (int k = k0; k < k0 + 8 && k < kPanel; ++k) {
-                m[k] -= lij * c[k - k0];
-                asm volatile("" : "+v"(m[k]));
-            }
-        }
+        for (int k = j + 1; k < kPanel; ++k) m[k] -= lij * col[k];
         __builtin_amdgcn_wave_barrier();
         asm volatile("" ::: "memory");
     }
@@ -295,6 +311,7 @@ __device__ __forceinline__ void fold_trailing(double *L, int c0, int w, int K)
         for (int u = 0; u < 4; ++u)
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+#pragma unroll 4
         for (int k = 0; k < w; ++k) {
             double ra[4], sb[4];
 #pragma unroll
@@ -369,52 +386,29 @@ __global__ __launch_bounds__(256) void k_fold_full(FoldArgs a)
         for (int k = tid; k < K; k += 256) out[k] = 0.0;
         return;
     }
-    // L y = c, then L^T a = y, panel by panel: each panel's diagonal block by
-    // one wavefront (lane i holds its unknown; the solved value reaches the
-    // lanes by lane reads), the other rows updated one per thread.
-    for (int c0 = 0; c0 < K; c0 += kPanel) {
-        const int w = K - c0 < kPanel ? K - c0 : kPanel;
-        if (wave == 0) {
-            double y = lane < w ? rhs[c0 + lane] : 0.0;
-#pragma unroll
-            for (int j = 0; j < kPanel; ++j) {
-                if (j >= w) continue;
-                const double yj = lane_bcast(y, j) * rdiag[c0 + j];
-                if (lane == j) y = yj;
-                if (lane > j && lane < w) y -= L[tri(c0 + lane, c0 + j)] * yj;
-            }
-            if (lane < w) rhs[c0 + lane] = y;
-        }
-        __syncthreads();
-        for (int r = c0 + w + tid; r < K; r += 256) {
-            double s = 0.0;
-            for (int k = 0; k < w; ++k) s += L[tri(r, c0 + k)] * rhs[c0 + k];
-            rhs[r] -= s;
-        }
-        __syncthreads();
+    // L y = c, then L^T a = y, by one wavefront with the unknowns in
+    // registers (lane l holds unknowns l and l + 64): each solved value
+    // reaches the lanes by a lane read, and every lane subtracts its
+    // share; no barriers.
+    if (wave != 0) return;
+    const int l0 = lane, l1 = lane + 64;
+    double y0 = l0 < K ? rhs[l0] : 0.0, y1 = l1 < K ? rhs[l1] : 0.0;
+    for (int k = 0; k < K; ++k) {
+        const double yk = (k < 64 ? lane_bcast(y0, k) : lane_bcast(y1, k - 64)) * rdiag[k];
+        if (l0 == k) y0 = yk;
+        if (l1 == k) y1 = yk;
+        if (l0 > k && l0 < K) y0 -= L[tri(l0, k)] * yk;
+        if (l1 > k && l1 < K) y1 -= L[tri(l1, k)] * yk;
     }
-    for (int c0 = (K - 1) / kPanel * kPanel; c0 >= 0; c0 -= kPanel) {
-        const int w = K - c0 < kPanel ? K - c0 : kPanel;
-        if (wave == 0) {
-            double y = lane < w ? rhs[c0 + lane] : 0.0;
-#pragma unroll
-            for (int j = kPanel - 1; j >= 0; --j) {
-                if (j >= w) continue;
-                const double aj = lane_bcast(y, j) * rdiag[c0 + j];
-                if (lane == j) y = aj;
-                if (lane < j) y -= L[tri(c0 + j, c0 + lane)] * aj;
-            }
-            if (lane < w) rhs[c0 + lane] = y;
-        }
-        __syncthreads();
-        for (int r = tid; r < c0; r += 256) {
-            double s = 0.0;
-            for (int k = 0; k < w; ++k) s += L[tri(c0 + k, r)] * rhs[c0 + k];
-            rhs[r] -= s;
-        }
-        __syncthreads();
+    for (int k = K - 1; k >= 0; --k) {
+        const double ak = (k < 64 ? lane_bcast(y0, k) : lane_bcast(y1, k - 64)) * rdiag[k];
+        if (l0 == k) y0 = ak;
+        if (l1 == k) y1 = ak;
+        if (l0 < k) y0 -= L[tri(k, l0)] * ak;
+        if (l1 < k) y1 -= L[tri(k, l1)] * ak;
     }
-    for (int k = tid; k < K; k += 256) out[k] = rhs[k];
+    if (l0 < K) out[l0] = y0;
+    if (l1 < K) out[l1] = y1;
 }
 
 // CDTF fold-in of one request per workgroup: a = 0, then `sweeps` passes
