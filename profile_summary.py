@@ -13,7 +13,8 @@ Reads
                  sends towards DRAM, in 32-byte units)
 or, with --ceiling FILE (the JSON line of `bench.py --gather-ceiling`),
 writes profiles/gather_ceiling.{json,md} and nothing else; with --serving
-FILE (the JSON line of `bench.py --serve-full`), profiles/serving_<workload>.md;
+FILE (the JSON line of `bench.py --serve-full`), profiles/serving_<workload>.md; with
+--kernels DIR --name NAME, a table of the kernels matching --match;
 otherwise writes
   profiles/k_accum_<workload>.md          per-kernel durations and traffic
   profiles/k_accum_<workload>_traffic.json bytes per launch of the row-
@@ -159,10 +160,34 @@ def write_serving(path, cmd):
     print(out)
 
 
+def write_kernels(stats_dir, name, cmd, pattern):
+    """Per-kernel durations of a `--kernel-trace --stats` run, the kernels
+    whose name contains `pattern` first, as a short table."""
+    stats = kernel_stats(stats_dir)
+    total = sum(float(r["TotalDurationNs"]) for r in stats)
+    sel = [r for r in stats if pattern in r["Name"]]
+    lines = [f"# Kernels matching `{pattern}`", "", f"Command: `{cmd}`", "",
+             "Per-kernel durations from `rocprofv3 --kernel-trace --stats` (microseconds; share of "
+             "all kernel time in the run).", "",
+             "| kernel | calls | avg us | min us | max us | share |", "|---|---|---|---|---|---|"]
+    for r in sorted(sel, key=lambda r: -float(r["TotalDurationNs"])):
+        lines.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs'])/1e3:.1f} | "
+                     f"{float(r['MinNs'])/1e3:.1f} | {float(r['MaxNs'])/1e3:.1f} | "
+                     f"{100*float(r['TotalDurationNs'])/total:.2f}% |")
+    out = os.path.join(ROOT, "profiles", f"{name}.md")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--ceiling", default=None)
     ap.add_argument("--serving", default=None)
+    ap.add_argument("--kernels", default=None, help="stats dir: write a table of matching kernels")
+    ap.add_argument("--name", default=None)
+    ap.add_argument("--match", default="k_fold")
+    ap.add_argument("--cmd", default="")
     ap.add_argument("--serving-cmd", default="python3 bench.py --workload sals-3way-1m-fp32 --serve-full")
     ap.add_argument("--ceiling-cmd", default="python3 bench.py --gather-ceiling")
     ap.add_argument("--stats")
@@ -189,6 +214,9 @@ def main():
         return
     if args.serving:
         write_serving(args.serving, args.serving_cmd)
+        return
+    if args.kernels:
+        write_kernels(args.kernels, args.name or "kernels", args.cmd, args.match)
         return
     if not (args.stats and args.workload and args.stats_cmd):
         ap.error("--stats, --workload and --stats-cmd are required without --ceiling")
