@@ -71,9 +71,12 @@ __device__ __forceinline__ void fold_block_sum2(double &u, double &v, double *sc
 constexpr int FOLD_CHUNK = 32;   // entries staged per step
 constexpr int FOLD_RB = 8;       // register block per thread (8 x 8 -> K <= 128)
 
-// Partial Gram of one chunk of one request (full rank, K <= 128): B and c
-// over the chunk's entries in the accumulation type, written as a record of
-// the lower triangle of B then c.
+// Partial Gram of one chunk of one request (K <= 128): B and c over the
+// chunk's entries in the accumulation type, written as a record of the lower
+// triangle of B then c.  Thread (ty, tx) accumulates rows ty + 16u and
+// columns tx + 16v of B for the blocks v <= u that reach below row K.  (The
+// entries' p rows come from k_fold_p, which forms them across the whole GPU:
+// forming them here, chunk by chunk, made this kernel twice as slow.)
 template <int PREC>
 __global__ __launch_bounds__(256) void k_fold_gram(FoldArgs a)
 {
@@ -96,6 +99,7 @@ __global__ __launch_bounds__(256) void k_fold_gram(FoldArgs a)
     TA racc = TA(0);   // c entry k = tid (tid < K)
 
     const TA *P = reinterpret_cast<const TA *>(a.P);
+    const int nub = (K + 15) / 16;   // row blocks that reach below K
     for (int64_t c0 = beg; c0 < end; c0 += FOLD_CHUNK) {
         const int cn = (int)(end - c0 < FOLD_CHUNK ? end - c0 : FOLD_CHUNK);
         for (int e = tid; e < cn * K; e += 256) Pc[e] = P[c0 * K + e];
@@ -111,9 +115,11 @@ __global__ __launch_bounds__(256) void k_fold_gram(FoldArgs a)
                 pc[u] = k2 < K ? Pc[j * K + k2] : TA(0);
             }
 #pragma unroll
-            for (int u = 0; u < FOLD_RB; ++u)
+            for (int u = 0; u < FOLD_RB; ++u) {
+                if (u >= nub) continue;
 #pragma unroll
-                for (int v = 0; v < FOLD_RB; ++v) acc[u][v] += pr[u] * pc[v];
+                for (int v = 0; v <= u; ++v) acc[u][v] += pr[u] * pc[v];
+            }
             if (tid < K) racc += (TA)xs[j] * Pc[j * K + tid];
         }
         __syncthreads();
@@ -122,15 +128,13 @@ __global__ __launch_bounds__(256) void k_fold_gram(FoldArgs a)
 #pragma unroll
     for (int u = 0; u < FOLD_RB; ++u)
 #pragma unroll
-        for (int v = 0; v < FOLD_RB; ++v) {
+        for (int v = 0; v <= u; ++v) {
             const int k1 = ty + 16 * u, k2 = tx + 16 * v;
             if (k1 < K && k2 <= k1) out[k1 * (k1 + 1) / 2 + k2] = acc[u][v];
         }
     if (tid < K) out[K * (K + 1) / 2 + tid] = racc;
 }
 
-// B (packed lower triangle) and c of request q in FP64: its chunk records
-// summed in chunk order (every thread of the block takes part).
 // Elements e0 + u * nb (u < U) of a request's nc chunk records, each summed
 // over the chunks in chunk order, CT chunks at a time.  The loads are not
 // conditional (indices past the ends are clamped and their values dropped),
