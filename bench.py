@@ -217,6 +217,17 @@ def roofline(ks, dt_s, workload, C):
             c = ceil["ceiling_glines_s"]
             lr.update({"ceiling_glines_s": c, "frac": rate / c, "ceiling_table": ceil["ceiling_table"]})
         out["l2_miss_line_rate"] = lr
+    hits = t.get("l2_hits_per_launch")
+    if miss and hits and ceil and ceil.get("hit_ceiling_glines_s"):
+        # each L2 request charged at the probe's rate for its kind: a launch
+        # that is bound by line requests takes hits / R_hit + misses / R_miss
+        rh, rm = ceil["hit_ceiling_glines_s"], ceil["ceiling_glines_s"]
+        model_ms = (hits / rh + miss / rm) / 1e9 * 1e3
+        out["l2_request_model"] = {
+            "hits_per_launch": hits, "misses_per_launch": miss, "hit_glines_s": rh,
+            "miss_glines_s": rm, "model_ms": model_ms, "frac": model_ms / avg_ms,
+            "note": "time the launch's L2 requests take at the gather probe's rates (hits at the "
+                    "1 MiB table's, misses at the 1 GiB table's), over the measured launch time"}
     return out
 
 
@@ -356,7 +367,7 @@ def gather_ceiling():
     waves, steps = 8192, 4096
     out = torch.empty(waves * 64, dtype=torch.float32, device="cuda")
     res = []
-    for mb in (4, 32, 128, 256, 1024, 4096):
+    for mb in (1, 2, 4, 32, 128, 256, 1024, 4096):
         rows = mb * (1 << 20) // 128
         table = torch.rand(rows * 32, dtype=torch.float32, device="cuda")
         tf.tf_probe_gather(table, rows, waves, steps, 1, out)     # warm-up (TLB, caches)
@@ -367,11 +378,14 @@ def gather_ceiling():
         log(f"gather {mb} MB table: {g:.1f} G lines/s ({g * 128:.0f} GB/s)")
         del table
     big = [r for r in res if r["table_mb"] == 1024][0]
+    small = [r for r in res if r["table_mb"] == 1][0]
     return {"probe": "tf_probe_gather", "waves": waves, "rows_per_half_wave": steps,
             "tables": res, "ceiling_glines_s": big["glines_s"], "ceiling_table": "1 GiB",
+            "hit_ceiling_glines_s": small["glines_s"], "hit_table": "1 MiB",
             "note": "random 128-byte rows, one coalesced load per half-wavefront, no index stream; "
                     "the 1 GiB table (far above the 8 x 4 MB of L2, above the 256 MB last-level "
-                    "cache) gives the L2-miss line-request ceiling"}
+                    "cache) gives the L2-miss line-request ceiling, the 1 MiB table (a quarter of "
+                    "one XCD's L2) the rate of requests that hit L2"}
 
 
 def c_tin_sweep(w, data, cs, tins, sweeps):

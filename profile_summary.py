@@ -127,6 +127,9 @@ def write_ceiling(path, cmd):
     lines += ["", f"Ceiling used for the row passes' L2-miss line rate: {c['ceiling_glines_s']:.1f} "
               f"G lines/s ({c['ceiling_table']} table: far above the 8 x 4 MB of L2 and the "
               "256 MB last-level cache)."]
+    if c.get("hit_ceiling_glines_s"):
+        lines += ["", f"Rate of requests served by L2: {c['hit_ceiling_glines_s']:.1f} G lines/s "
+                  f"({c['hit_table']} table: a quarter of one XCD's 4 MB L2)."]
     with open(os.path.join(ROOT, "profiles", "gather_ceiling.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
     print(os.path.join(ROOT, "profiles", "gather_ceiling.md"))
@@ -333,6 +336,12 @@ def main():
             lines += ["", f"Its bounded roofline: {rf['achieved']:.0f} GB/s of HBM-side traffic, frac "
                       f"{rf['frac']:.3f}; L2-miss lines at {rf['l2_miss_line_rate']['achieved_glines_s']:.1f} "
                       f"G/s, {rf['l2_miss_line_rate'].get('frac', 0):.2f} of the gather ceiling."]
+            rm = rf.get("l2_request_model")
+            if rm:
+                lines += ["", f"Its L2 requests at the gather probe's rates ({rm['hits_per_launch']:.4g} "
+                          f"hits at {rm['hit_glines_s']:.1f} G/s, {rm['misses_per_launch']:.4g} misses "
+                          f"at {rm['miss_glines_s']:.1f} G/s) take {rm['model_ms']:.2f} ms: "
+                          f"{rm['frac']:.2f} of the measured launch."]
     out = os.path.join(ROOT, "profiles", f"k_accum_{args.workload}.md")
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
