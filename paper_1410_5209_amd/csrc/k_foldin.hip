@@ -228,79 +228,134 @@ __device__ __forceinline__ double fold_rsqrt(double d)
     return r;
 }
 
+// 1 / d for d > 0: the hardware estimate and two steps of Newton's
+// iteration r <- r + r (1 - d r), each roughly doubling the correct bits.
+__device__ __forceinline__ double fold_rcp(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return r;
+}
+
+// Width of a panel: WC columns when WC > 0 (a full panel, whose loop bounds
+// are then known when compiling), else the run-time w.
+template <int WC>
+__device__ __forceinline__ int panel_w(int w) { return WC > 0 ? WC : w; }
+
 // Cholesky of the diagonal block (rows and columns c0 .. c0 + w - 1, w <=
 // 32) of the packed triangle, in place, by one wavefront: lane i holds row i
-// of the block in registers.  Step j: lane j's pivot reaches every lane by
-// lane reads; lanes i > j form L(i, j) and publish it in col[]; every lane
-// updates its row from there (LDS accesses of one wavefront stay in program
-// order).  rdiag[c0 + j] = 1 / L(j, j).  A non-positive pivot sets *failed
+// of the block in registers.  Step j: lane j's pivot d reaches every lane by
+// lane reads, and every lane updates its row by M(i, k) -= M(i, j) M(k, j) / d
+// (= L(i, j) L(k, j)), with the unscaled M(k, j) read from colu[], where lane
+// k published it at the end of the step before.  So the LDS round trip runs
+// beside the pivot's reciprocal, and the reciprocal square root that scales
+// column j runs beside the next step (two buffers; LDS accesses of one
+// wavefront stay in program order).  Lanes i > j keep L(i, j) = M(i, j) /
+// sqrt(d); rdiag[c0 + j] = 1 / L(j, j).  A non-positive pivot sets *failed
 // and the factorisation goes on with 1 (the request is then reported).
-__device__ __forceinline__ void fold_diag_block(double *L, int c0, int w, double *rdiag, double *col, int *failed)
+// Lanes with no row, and registers k beyond a lane's row, are updated as
+// scratch and never stored.
+template <int WC>
+__device__ __forceinline__ void fold_diag_block(double *L, int c0, int w_rt, double *rdiag,
+                                                double (*colu)[64], int *failed)
 {
-    const int i = threadIdx.x & 63;
+    const int w = panel_w<WC>(w_rt);
+    int i = threadIdx.x & 63;
+    asm volatile("" : "+v"(i));   // lane tests stay in this call, not held across panels
     const bool in = i < w;
     double m[kPanel];
 #pragma unroll
-    for (int k = 0; k < kPanel; ++k) m[k] = (in && k <= i) ? L[tri(c0 + i, c0 + k)] : 0.0;
+    for (int k = 0; k < kPanel; ++k) {
+        const bool own = in && k <= i;
+        const double v = L[own ? tri(c0 + i, c0 + k) : 0];
+        m[k] = own ? v : 0.0;
+    }
+    colu[0][i] = m[0];
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
+    double rd = 0.0;
+    bool bad = false;
 #pragma unroll
     for (int j = 0; j < kPanel; ++j) {
         if (j >= w) continue;   // (not break: the loop must unroll fully)
+        double cu[kPanel];
+#pragma unroll
+        for (int k = j + 1; k < kPanel; ++k) cu[k] = colu[j & 1][k];
         const double d = lane_bcast(m[j], j);
         const bool ok = d > 0.0;
-        const double dd = ok ? d : 1.0, rinv = fold_rsqrt(dd), ljj = dd * rinv;
-        if (i == 0 && !ok) *failed = 1;
-        double lij = 0.0;
-        if (in && i > j) {
-            lij = m[j] * rinv;
-            m[j] = lij;
-            col[i] = lij;
-        }
-        if (i == j) {
-            m[j] = ljj;
-            rdiag[c0 + j] = rinv;
-        }
-        __builtin_amdgcn_wave_barrier();
-        asm volatile("" ::: "memory");
-        // M(i, k) -= L(i, j) L(k, j) for k > j (lanes with no row, or k
-        // beyond their row, update scratch registers that are not stored)
+        bad = bad || !ok;
+        const double dd = ok ? d : 1.0;
+        const double mij = m[j], f = mij * fold_rcp(dd);
 #pragma unroll
-        for (int k = j + 1; k < kPanel; ++k) m[k] -= lij * col[k];
+        for (int k = j + 1; k < kPanel; ++k) m[k] -= f * cu[k];
+        if (j + 1 < kPanel) colu[(j + 1) & 1][i] = m[j + 1];
+        const double rinv = fold_rsqrt(dd);
+        m[j] = i == j ? dd * rinv : (i > j ? mij * rinv : mij);
+        rd = i == j ? rinv : rd;
         __builtin_amdgcn_wave_barrier();
         asm volatile("" ::: "memory");
     }
+    if (in) rdiag[c0 + i] = rd;
+    if (i == 0 && bad) *failed = 1;
 #pragma unroll
     for (int k = 0; k < kPanel; ++k)
         if (in && k <= i) L[tri(c0 + i, c0 + k)] = m[k];
 }
 
-// Rows below the diagonal block: L(r, c0..) = A(r, c0..) L11^{-T}, one
-// thread per row, forward substitution against the block.
-__device__ __forceinline__ void fold_panel_rows(double *L, int c0, int w, int K, const double *rdiag)
+// Rows below the diagonal block: L(r, c0..) = A(r, c0..) L11^{-T}, by
+// forward substitution against the block, two lanes per row: lane h of the
+// pair holds the row's columns 2u + h, sums its half of each dot product
+// (two partial sums), and one lane swap adds the other half, so both lanes
+// form the same x(k) (a + b and b + a are equal in floating point).
+template <int WC>
+__device__ __forceinline__ void fold_panel_rows(double *L, int c0, int w_rt, int K, const double *rdiag)
 {
-    for (int r = c0 + w + (int)threadIdx.x; r < K; r += blockDim.x) {
+    constexpr int H = kPanel / 2;
+    const int w = panel_w<WC>(w_rt);
+    const int h = threadIdx.x & 1;
+    for (int r = c0 + w + (int)(threadIdx.x >> 1); r < K; r += (int)(blockDim.x >> 1)) {
         const int base = tri(r, c0);
-        double x[kPanel];
+        double xs[H];
 #pragma unroll
-        for (int k = 0; k < kPanel; ++k) x[k] = k < w ? L[base + k] : 0.0;
+        for (int u = 0; u < H; ++u) {
+            const bool in = 2 * u + h < w;
+            const double v = L[base + (in ? 2 * u + h : 0)];
+            xs[u] = in ? v : 0.0;
+        }
 #pragma unroll
         for (int k = 0; k < kPanel; ++k) {
             if (k >= w) continue;
-            double s = x[k];
             const int bk = tri(c0 + k, c0);
+            double p[2] = {0.0, 0.0};
 #pragma unroll
-            for (int t = 0; t < k; ++t) s -= x[t] * L[bk + t];
-            x[k] = s * rdiag[c0 + k];
+            for (int u = 0; 2 * u + 1 < k + 1; ++u) {
+                // column 2u + h < k: lane 1 of the pair has one term fewer when k is odd
+                const bool in = 2 * u + h < k;
+                const double l = L[bk + (in ? 2 * u + h : 0)];
+                p[u & 1] -= xs[u] * (in ? l : 0.0);
+            }
+            double part = p[0] + p[1];
+            part += dpp_mov<0xB1>(part);
+            const double own = (k & 1) == h ? xs[k >> 1] : 0.0;
+            const double a = own + dpp_mov<0xB1>(own);   // A(r, c0 + k), from the lane that holds it
+            const double xk = (a + part) * rdiag[c0 + k];
+            if ((k & 1) == h) xs[k >> 1] = xk;
         }
 #pragma unroll
-        for (int k = 0; k < kPanel; ++k)
-            if (k < w) L[base + k] = x[k];
+        for (int u = 0; u < H; ++u)
+            if (2 * u + h < w) L[base + 2 * u + h] = xs[u];
     }
 }
 
 // Trailing update of the rows and columns after the panel, in 4 x 4 tiles
 // of the lower triangle: A(r, s) -= sum_k L(r, k) L(s, k) over the panel.
-__device__ __forceinline__ void fold_trailing(double *L, int c0, int w, int K)
+// A tile's rows past K read row K - 1 instead (those sums are not stored),
+// so the 32 reads of each group of four columns are issued together.
+template <int WC>
+__device__ __forceinline__ void fold_trailing(double *L, int c0, int w_rt, int K)
 {
+    const int w = panel_w<WC>(w_rt);
     const int c1 = c0 + w, n = K - c1;
     if (n <= 0) return;
     const int T = (n + 3) / 4, ntile = T * (T + 1) / 2;
@@ -310,23 +365,37 @@ __device__ __forceinline__ void fold_trailing(double *L, int c0, int w, int K)
         while (ti * (ti + 1) / 2 > t) --ti;
         const int tj = t - ti * (ti + 1) / 2;
         const int r0 = c1 + 4 * ti, s0 = c1 + 4 * tj;
+        int br[4], bs[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            br[u] = tri(r0 + u < K ? r0 + u : K - 1, c0);
+            bs[u] = tri(s0 + u < K ? s0 + u : K - 1, c0);
+        }
         double acc[4][4];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-#pragma unroll 4
-        for (int k = 0; k < w; ++k) {
-            double ra[4], sb[4];
+#pragma unroll 1
+        for (int k0 = 0; k0 < w; k0 += 4) {
+            double ra[4][4], sb[4][4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                ra[u] = r0 + u < K ? L[tri(r0 + u, c0 + k)] : 0.0;
-                sb[u] = s0 + u < K ? L[tri(s0 + u, c0 + k)] : 0.0;
+            for (int kk = 0; kk < 4; ++kk) {
+                const bool kin = WC > 0 || k0 + kk < w;
+                const int k = kin ? k0 + kk : 0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const double a = L[br[u] + k], b = L[bs[u] + k];
+                    ra[kk][u] = kin ? a : 0.0;
+                    sb[kk][u] = kin ? b : 0.0;
+                }
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u][v] += ra[u] * sb[v];
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[u][v] += ra[kk][u] * sb[kk][v];
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
@@ -336,6 +405,20 @@ __device__ __forceinline__ void fold_trailing(double *L, int c0, int w, int K)
                 if (r < K && c <= r) L[tri(r, c)] -= acc[u][v];
             }
     }
+}
+
+// One panel of the blocked Cholesky: its diagonal block by wavefront 0, the
+// rows below it one per thread, then the trailing lower triangle.
+template <int WC>
+__device__ __forceinline__ void fold_panel(double *L, int c0, int w, int K, double *rdiag,
+                                           double (*colu)[64], int *failed)
+{
+    if ((threadIdx.x >> 6) == 0) fold_diag_block<WC>(L, c0, w, rdiag, colu, failed);
+    __syncthreads();
+    fold_panel_rows<WC>(L, c0, w, K, rdiag);
+    __syncthreads();
+    fold_trailing<WC>(L, c0, w, K);
+    __syncthreads();
 }
 
 // Full-rank fold-in of one request per workgroup (K <= 128): the chunk
@@ -370,19 +453,15 @@ __global__ __launch_bounds__(256) void k_fold_full(FoldArgs a)
     // one wavefront, the rows below it one per thread, then the trailing
     // lower triangle in 4 x 4 tiles (three workgroup barriers per panel).
     __shared__ double rdiag[kFoldMaxKFull];
-    __shared__ double col[kPanel];
+    __shared__ double colu[2][64];
     __shared__ int failed;
     const int wave = tid >> 6, lane = tid & 63;
     if (tid == 0) failed = 0;
     __syncthreads();
     for (int c0 = 0; c0 < K; c0 += kPanel) {
         const int w = K - c0 < kPanel ? K - c0 : kPanel;
-        if (wave == 0) fold_diag_block(L, c0, w, rdiag, col, &failed);
-        __syncthreads();
-        fold_panel_rows(L, c0, w, K, rdiag);
-        __syncthreads();
-        fold_trailing(L, c0, w, K);
-        __syncthreads();
+        if (w == kPanel) fold_panel<kPanel>(L, c0, w, K, rdiag, colu, &failed);
+        else fold_panel<0>(L, c0, w, K, rdiag, colu, &failed);
     }
     if (tid == 0 && a.req_status) a.req_status[q] = failed ? TF_E_NUMERIC : TF_OK;
     if (failed) {
@@ -391,25 +470,91 @@ __global__ __launch_bounds__(256) void k_fold_full(FoldArgs a)
         return;
     }
     // L y = c, then L^T a = y, by one wavefront with the unknowns in
-    // registers (lane l holds unknowns l and l + 64): each solved value
-    // reaches the lanes by a lane read, and every lane subtracts its
-    // share; no barriers.
+    // registers (lane l holds unknowns l and l + 64, and their pivots'
+    // reciprocals): each solved value reaches the lanes by a lane read, and
+    // every lane subtracts its share; no barriers.  The factor's entries
+    // are read eight columns at a time ahead of the steps that use them.
     if (wave != 0) return;
     const int l0 = lane, l1 = lane + 64;
+    const int K0 = K < 64 ? K : 64;
+    const double rd0 = l0 < K ? rdiag[l0] : 0.0, rd1 = l1 < K ? rdiag[l1] : 0.0;
     double y0 = l0 < K ? rhs[l0] : 0.0, y1 = l1 < K ? rhs[l1] : 0.0;
-    for (int k = 0; k < K; ++k) {
-        const double yk = (k < 64 ? lane_bcast(y0, k) : lane_bcast(y1, k - 64)) * rdiag[k];
-        if (l0 == k) y0 = yk;
-        if (l1 == k) y1 = yk;
-        if (l0 > k && l0 < K) y0 -= L[tri(l0, k)] * yk;
-        if (l1 > k && l1 < K) y1 -= L[tri(l1, k)] * yk;
+    constexpr int SB = 8;
+    for (int kb = 0; kb < K0; kb += SB) {
+        double a0[SB], a1[SB];
+#pragma unroll
+        for (int t = 0; t < SB; ++t) {
+            const int k = kb + t;
+            const bool v0 = k < K0 && l0 > k && l0 < K, v1 = k < K0 && l1 < K;
+            const double e0 = L[v0 ? tri(l0, k) : 0], e1 = L[v1 ? tri(l1, k) : 0];
+            a0[t] = v0 ? e0 : 0.0;
+            a1[t] = v1 ? e1 : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < SB; ++t) {
+            const int k = kb + t;
+            if (k >= K0) continue;
+            const double yk = lane_bcast(y0 * rd0, k);
+            if (l0 == k) y0 = yk;
+            y0 -= a0[t] * yk;
+            y1 -= a1[t] * yk;
+        }
     }
-    for (int k = K - 1; k >= 0; --k) {
-        const double ak = (k < 64 ? lane_bcast(y0, k) : lane_bcast(y1, k - 64)) * rdiag[k];
-        if (l0 == k) y0 = ak;
-        if (l1 == k) y1 = ak;
-        if (l0 < k) y0 -= L[tri(k, l0)] * ak;
-        if (l1 < k) y1 -= L[tri(k, l1)] * ak;
+    for (int kb = 64; kb < K; kb += SB) {
+        double a1[SB];
+#pragma unroll
+        for (int t = 0; t < SB; ++t) {
+            const int k = kb + t;
+            const bool v1 = k < K && l1 > k && l1 < K;
+            const double e1 = L[v1 ? tri(l1, k) : 0];
+            a1[t] = v1 ? e1 : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < SB; ++t) {
+            const int k = kb + t;
+            if (k >= K) continue;
+            const double yk = lane_bcast(y1 * rd1, k - 64);
+            if (l1 == k) y1 = yk;
+            y1 -= a1[t] * yk;
+        }
+    }
+    for (int kb = K - 1; kb >= 64; kb -= SB) {
+        double b0[SB], b1[SB];
+#pragma unroll
+        for (int t = 0; t < SB; ++t) {
+            const int k = kb - t;
+            const bool v0 = k >= 64, v1 = k >= 64 && l1 < k;
+            const double e0 = L[v0 ? tri(k, l0) : 0], e1 = L[v1 ? tri(k, l1) : 0];
+            b0[t] = v0 ? e0 : 0.0;
+            b1[t] = v1 ? e1 : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < SB; ++t) {
+            const int k = kb - t;
+            if (k < 64) continue;
+            const double ak = lane_bcast(y1 * rd1, k - 64);
+            if (l1 == k) y1 = ak;
+            y0 -= b0[t] * ak;
+            y1 -= b1[t] * ak;
+        }
+    }
+    for (int kb = K0 - 1; kb >= 0; kb -= SB) {
+        double b0[SB];
+#pragma unroll
+        for (int t = 0; t < SB; ++t) {
+            const int k = kb - t;
+            const bool v0 = k >= 0 && l0 < k;
+            const double e0 = L[v0 ? tri(k, l0) : 0];
+            b0[t] = v0 ? e0 : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < SB; ++t) {
+            const int k = kb - t;
+            if (k < 0) continue;
+            const double ak = lane_bcast(y0 * rd0, k);
+            if (l0 == k) y0 = ak;
+            y0 -= b0[t] * ak;
+        }
     }
     if (l0 < K) out[l0] = y0;
     if (l1 < K) out[l1] = y1;
