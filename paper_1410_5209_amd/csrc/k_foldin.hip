@@ -216,7 +216,7 @@ __device__ __forceinline__ double wave_sum(double v)
     return (lane_bcast(v, 0) + lane_bcast(v, 16)) + (lane_bcast(v, 32) + lane_bcast(v, 48));
 }
 
-constexpr int kPanel = 32;   // columns per panel of the blocked Cholesky
+constexpr int kPanel = 16;   // columns per panel of the blocked Cholesky
 
 // 1 / sqrt(d) for d > 0: the hardware estimate and two steps of Newton's
 // iteration r <- r (3 - d r^2) / 2, each roughly doubling the correct bits.
@@ -244,18 +244,19 @@ template <int WC>
 __device__ __forceinline__ int panel_w(int w) { return WC > 0 ? WC : w; }
 
 // Cholesky of the diagonal block (rows and columns c0 .. c0 + w - 1, w <=
-// 32) of the packed triangle, in place, by one wavefront: lane i holds row i
-// of the block in registers.  Step j: lane j's pivot d reaches every lane by
-// lane reads, and every lane updates its row by M(i, k) -= M(i, j) M(k, j) / d
-// (= L(i, j) L(k, j)), with the unscaled M(k, j) read from colu[], where lane
-// k published it at the end of the step before.  So the LDS round trip runs
-// beside the pivot's reciprocal, and the reciprocal square root that scales
-// column j runs beside the next step (two buffers; LDS accesses of one
-// wavefront stay in program order).  Lanes i > j keep L(i, j) = M(i, j) /
-// sqrt(d); rdiag[c0 + j] = 1 / L(j, j).  A non-positive pivot sets *failed
-// and the factorisation goes on with 1 (the request is then reported).
-// Lanes with no row, and registers k beyond a lane's row, are updated as
-// scratch and never stored.
+// 16) of the packed triangle, in place, by one wavefront: lane i holds row i
+// of the block in registers.  Step j updates every row by M(i, k) -=
+// f_i M(k, j) with f_i = M(i, j) / d_j (= L(i, j) L(k, j)), d_j the pivot.
+// The loop carries only unscaled values, each step's chain being short:
+// right after column j + 1 is updated, lane j + 1's new pivot reaches every
+// lane by lane reads and each lane forms its next f beside the rest of the
+// step's row updates, and lane k publishes M(k, j + 1) in colu[] for the next
+// step's reads (two buffers; LDS accesses of one wavefront stay in program
+// order).  Lane i's pivot stays in m[i]; afterwards it takes 1 / sqrt of it,
+// publishes that as rdiag[c0 + i], and scales its row: L(i, j) = M(i, j) /
+// sqrt(d_j), L(i, i) = sqrt(d_i).  A non-positive pivot sets *failed (the
+// request is then reported and its row not used).  Lanes with no row, and
+// registers k beyond a lane's row, are updated as scratch and never stored.
 template <int WC>
 __device__ __forceinline__ void fold_diag_block(double *L, int c0, int w_rt, double *rdiag,
                                                 double (*colu)[64], int *failed)
@@ -274,30 +275,43 @@ __device__ __forceinline__ void fold_diag_block(double *L, int c0, int w_rt, dou
     colu[0][i] = m[0];
     __builtin_amdgcn_wave_barrier();
     asm volatile("" ::: "memory");
-    double rd = 0.0;
-    bool bad = false;
+    double cu[kPanel];
+#pragma unroll
+    for (int k = 1; k < kPanel; ++k) cu[k] = colu[0][k];
+    double f = m[0] * fold_rcp(lane_bcast(m[0], 0));
 #pragma unroll
     for (int j = 0; j < kPanel; ++j) {
         if (j >= w) continue;   // (not break: the loop must unroll fully)
-        double cu[kPanel];
+        double fn = 0.0, cn[kPanel];
+        if (j + 1 < w) {
+            m[j + 1] -= f * cu[j + 1];
+            colu[(j + 1) & 1][i] = m[j + 1];
+            __builtin_amdgcn_wave_barrier();
+            asm volatile("" ::: "memory");
 #pragma unroll
-        for (int k = j + 1; k < kPanel; ++k) cu[k] = colu[j & 1][k];
-        const double d = lane_bcast(m[j], j);
-        const bool ok = d > 0.0;
-        bad = bad || !ok;
-        const double dd = ok ? d : 1.0;
-        const double mij = m[j], f = mij * fold_rcp(dd);
+            for (int k = j + 2; k < kPanel; ++k) cn[k] = colu[(j + 1) & 1][k];
+            fn = m[j + 1] * fold_rcp(lane_bcast(m[j + 1], j + 1));
+        }
 #pragma unroll
-        for (int k = j + 1; k < kPanel; ++k) m[k] -= f * cu[k];
-        if (j + 1 < kPanel) colu[(j + 1) & 1][i] = m[j + 1];
-        const double rinv = fold_rsqrt(dd);
-        m[j] = i == j ? dd * rinv : (i > j ? mij * rinv : mij);
-        rd = i == j ? rinv : rd;
-        __builtin_amdgcn_wave_barrier();
-        asm volatile("" ::: "memory");
+        for (int k = j + 2; k < kPanel; ++k) m[k] -= f * cu[k];
+#pragma unroll
+        for (int k = j + 2; k < kPanel; ++k) cu[k] = cn[k];
+        f = fn;
     }
-    if (in) rdiag[c0 + i] = rd;
-    if (i == 0 && bad) *failed = 1;
+    double di = 1.0;
+#pragma unroll
+    for (int k = 0; k < kPanel; ++k) di = k == i ? m[k] : di;
+    const bool ok = !in || di > 0.0;
+    const double rinv = fold_rsqrt(in ? di : 1.0);
+    if (in) rdiag[c0 + i] = rinv;
+    if (__ballot(!ok) != 0 && i == 0) *failed = 1;
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int k = 0; k < kPanel; ++k) {
+        const double rk = rdiag[c0 + (k < w ? k : 0)];
+        m[k] = k == i ? di * rinv : m[k] * rk;
+    }
 #pragma unroll
     for (int k = 0; k < kPanel; ++k)
         if (in && k <= i) L[tri(c0 + i, c0 + k)] = m[k];
@@ -449,7 +463,7 @@ __global__ __launch_bounds__(256) void k_fold_full(FoldArgs a)
     __syncthreads();
 
     // Cholesky L L^T of the packed lower triangle (text after Theorem 1),
-    // right-looking in panels of 32 columns: the panel's diagonal block by
+    // right-looking in panels of 16 columns: the panel's diagonal block by
     // one wavefront, the rows below it one per thread, then the trailing
     // lower triangle in 4 x 4 tiles (three workgroup barriers per panel).
     __shared__ double rdiag[kFoldMaxKFull];
