@@ -578,15 +578,19 @@ __global__ __launch_bounds__(256) void k_fold_full(FoldArgs a)
 // over k = 0..K-1 of the C = 1 update a_k = sum_j rhat_j p_jk /
 // (lambda_i + sum_j p_jk^2), rhat = r + a_k p_k, r = x - P a (Section 3.1).
 // With B = P^T P and c = P^T x the numerator is c_k - sum_{k' != k} B_kk'
-// a_k', so each update needs one dot product of length K against the
-// request's B (in LDS) instead of two passes over its entries.  One
-// wavefront does the sweeps (lane l holds a_l and a_{l+64}); the other
-// wavefronts only help sum the chunk records.
+// a_k' = g_k + B_kk a_k, where g = c - B a (= P^T r) is kept up to date:
+// when a_k changes by delta, every g_i loses delta B_ik.  So an update needs
+// two lane reads (g_k, a_k) and one vector update instead of a sum over the
+// request's entries or over the wavefront.  One wavefront does the sweeps
+// (lane l holds a_l, g_l and a_{l+64}, g_{l+64}), reading the columns of B
+// eight coordinates ahead; the other wavefronts only help sum the chunk
+// records.
 template <int PREC>
 __global__ __launch_bounds__(256) void k_fold_cdtf(FoldArgs a)
 {
     using TA = typename Types<PREC>::TA;
     extern __shared__ double smem[];
+    __shared__ double bdiag[kFoldMaxKFull], rden[kFoldMaxKFull];
     const int K = a.K;
     const int q = blockIdx.x;
     const int64_t m = a.req_ptr[q + 1] - a.req_ptr[q];
@@ -603,20 +607,44 @@ __global__ __launch_bounds__(256) void k_fold_cdtf(FoldArgs a)
     __syncthreads();
     if (tid >= 64) return;
     const double lam = a.reg_mode ? a.lambda * (double)m : a.lambda;
+    for (int k = tid; k < K; k += 64) {
+        const double bkk = B[tri(k, k)];
+        bdiag[k] = bkk;
+        rden[k] = 1.0 / (lam + bkk);
+    }
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
     const int l0 = tid, l1 = tid + 64;
     double a0 = 0.0, a1 = 0.0;
-    auto bidx = [](int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; };
+    double g0 = l0 < K ? c[l0] : 0.0, g1 = l1 < K ? c[l1] : 0.0;
+    auto bidx = [](int i, int j) { return i >= j ? tri(i, j) : tri(j, i); };
+    constexpr int SB = 8;
     for (int s = 0; s < a.sweeps; ++s) {
-        for (int k = 0; k < K; ++k) {
-            // sum over k' != k of B_kk' a_k' (fixed order over the wavefront)
-            double t = 0.0;
-            if (l0 < K && l0 != k) t += B[bidx(k, l0)] * a0;
-            if (l1 < K && l1 != k) t += B[bidx(k, l1)] * a1;
-            t = wave_sum(t);
-            const double bkk = B[k * (k + 1) / 2 + k];
-            const double ak = (c[k] - t) / (lam + bkk);
-            if (l0 == k) a0 = ak;
-            if (l1 == k) a1 = ak;
+        for (int kb = 0; kb < K; kb += SB) {
+            double e0[SB], e1[SB], bk[SB], rk[SB];
+#pragma unroll
+            for (int t = 0; t < SB; ++t) {
+                const int k = kb + t;
+                const bool kin = k < K, v0 = kin && l0 < K, v1 = kin && l1 < K;
+                const double x0 = B[v0 ? bidx(l0, k) : 0], x1 = B[v1 ? bidx(l1, k) : 0];
+                e0[t] = v0 ? x0 : 0.0;
+                e1[t] = v1 ? x1 : 0.0;
+                bk[t] = bdiag[kin ? k : 0];
+                rk[t] = rden[kin ? k : 0];
+            }
+#pragma unroll
+            for (int t = 0; t < SB; ++t) {
+                const int k = kb + t;
+                if (k >= K) continue;
+                const double gk = k < 64 ? lane_bcast(g0, k) : lane_bcast(g1, k - 64);
+                const double ak0 = k < 64 ? lane_bcast(a0, k) : lane_bcast(a1, k - 64);
+                const double ak = (gk + bk[t] * ak0) * rk[t];
+                const double delta = ak - ak0;
+                if (l0 == k) a0 = ak;
+                if (l1 == k) a1 = ak;
+                g0 -= delta * e0[t];
+                g1 -= delta * e1[t];
+            }
         }
     }
     if (l0 < K) out[l0] = a0;
