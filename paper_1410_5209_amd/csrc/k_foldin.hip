@@ -422,7 +422,7 @@ __device__ __forceinline__ void fold_trailing(double *L, int c0, int w_rt, int K
 }
 
 // One panel of the blocked Cholesky: its diagonal block by wavefront 0, the
-// rows below it one per thread, then the trailing lower triangle.
+// rows below it by lane pairs, then the trailing lower triangle.
 template <int WC>
 __device__ __forceinline__ void fold_panel(double *L, int c0, int w, int K, double *rdiag,
                                            double (*colu)[64], int *failed)
@@ -464,7 +464,7 @@ __global__ __launch_bounds__(256) void k_fold_full(FoldArgs a)
 
     // Cholesky L L^T of the packed lower triangle (text after Theorem 1),
     // right-looking in panels of 16 columns: the panel's diagonal block by
-    // one wavefront, the rows below it one per thread, then the trailing
+    // one wavefront, the rows below it by lane pairs, then the trailing
     // lower triangle in 4 x 4 tiles (three workgroup barriers per panel).
     __shared__ double rdiag[kFoldMaxKFull];
     __shared__ double colu[2][64];
