@@ -1311,6 +1311,23 @@ tf_status time_mode(tf_ctx *c, int n, int CP, int npend, int T_in, void *scratch
     return TF_OK;
 }
 
+// Mode n's pass time for the tiles being tried: the shorter of two trials
+// (one trial's noise, a few percent, is as large as the differences between
+// neighbouring tiles).
+tf_status time_mode_best(tf_ctx *c, int n, int C, int T_in, void *scratch, double *t)
+{
+    *t = 1e300;
+    for (int rep = 0; rep < 2; ++rep) {
+        int CP = 0, npend = 0;
+        tf_status s = trial_slabs(c, C, &CP, &npend);
+        if (s != TF_OK) return s;
+        double t1 = 0.0, t2 = 0.0;
+        if ((s = time_mode(c, n, CP, npend, T_in, scratch, &t1, &t2)) != TF_OK) return s;
+        *t = std::min(*t, t1 + (T_in - 1) * t2);
+    }
+    return TF_OK;
+}
+
 }  // namespace
 
 extern "C" tf_status tf_autotune(tf_ctx *ctx, int32_t T_in, const int32_t *h_cands, int32_t ncand,
@@ -1365,17 +1382,14 @@ extern "C" tf_status tf_autotune(tf_ctx *ctx, int32_t T_in, const int32_t *h_can
     if (tune_tiles) {
         static const int lanes[] = {1, 2, 4, 8};
         static const int chunks[] = {1024, 4096, 16384};
-        int CP = 0, npend = 0;
         for (int n = 0; n < ctx->N; ++n) {
             double tbest = 1e300;
             int bl = ctx->m[n].lane_nnz, bs = ctx->m[n].split_threshold, bc = ctx->m[n].chunk_nnz;
             for (int lane : lanes)
                 for (int ch : chunks) {
                     if ((s = apply_plan(ctx, n, lane, 2 * ch, ch)) != TF_OK) return s;
-                    if ((s = trial_slabs(ctx, bestC, &CP, &npend)) != TF_OK) return s;
-                    double t1 = 0.0, t2 = 0.0;
-                    if ((s = time_mode(ctx, n, CP, npend, T_in, scratch, &t1, &t2)) != TF_OK) return s;
-                    const double t = t1 + (T_in - 1) * t2;
+                    double t = 0.0;
+                    if ((s = time_mode_best(ctx, n, bestC, T_in, scratch, &t)) != TF_OK) return s;
                     if (t < tbest) { tbest = t; bl = lane; bs = 2 * ch; bc = ch; }
                 }
             if ((s = apply_plan(ctx, n, bl, bs, bc)) != TF_OK) return s;
@@ -1386,10 +1400,7 @@ extern "C" tf_status tf_autotune(tf_ctx *ctx, int32_t T_in, const int32_t *h_can
                 double tf_[2];
                 for (int p = 0; p < 2; ++p) {
                     ctx->m[n].persistent = p == 1;
-                    if ((s = trial_slabs(ctx, bestC, &CP, &npend)) != TF_OK) return s;
-                    double t1 = 0.0, t2 = 0.0;
-                    if ((s = time_mode(ctx, n, CP, npend, T_in, scratch, &t1, &t2)) != TF_OK) return s;
-                    tf_[p] = t1 + (T_in - 1) * t2;
+                    if ((s = time_mode_best(ctx, n, bestC, T_in, scratch, &tf_[p])) != TF_OK) return s;
                 }
                 ctx->m[n].persistent = tf_[1] < tf_[0];
             }
