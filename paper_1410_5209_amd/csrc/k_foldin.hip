@@ -205,17 +205,6 @@ __device__ __forceinline__ double lane_bcast(double v, int j)
     return __hiloint2double(hi, lo);
 }
 
-// Sum over the wavefront, the same in every lane, in a fixed order: DPP
-// steps within each row of 16 lanes, then the four row sums by lane reads.
-__device__ __forceinline__ double wave_sum(double v)
-{
-    v += dpp_mov<0xB1>(v);    // quad_perm 1,0,3,2
-    v += dpp_mov<0x4E>(v);    // quad_perm 2,3,0,1
-    v += dpp_mov<0x141>(v);   // row_half_mirror
-    v += dpp_mov<0x140>(v);   // row_mirror
-    return (lane_bcast(v, 0) + lane_bcast(v, 16)) + (lane_bcast(v, 32) + lane_bcast(v, 48));
-}
-
 constexpr int kPanel = 16;   // columns per panel of the blocked Cholesky
 
 // 1 / sqrt(d) for d > 0: the hardware estimate and two steps of Newton's
