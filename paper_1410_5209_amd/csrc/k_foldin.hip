@@ -73,8 +73,9 @@ constexpr int FOLD_RB = 8;       // register block per thread (8 x 8 -> K <= 128
 
 // Partial Gram of one chunk of one request (K <= 128): B and c over the
 // chunk's entries in the accumulation type, written as a record of the lower
-// triangle of B then c.  Thread (ty, tx) accumulates rows ty + 16u and
-// columns tx + 16v of B for the blocks v <= u that reach below row K.  (The
+// triangle of B then c.  FP32: on the matrix cores (below).  FP64: thread
+// (ty, tx) accumulates rows ty + 16u and columns tx + 16v of B for the
+// blocks v <= u that reach below row K.  (The
 // entries' p rows come from k_fold_p, which forms them across the whole GPU:
 // forming them here, chunk by chunk, made this kernel twice as slow.)
 template <int PREC>
@@ -99,6 +100,65 @@ __global__ __launch_bounds__(256) void k_fold_gram(FoldArgs a)
     TA racc = TA(0);   // c entry k = tid (tid < K)
 
     const TA *P = reinterpret_cast<const TA *>(a.P);
+    if constexpr (PREC != P_F64) {
+        // FP32 accumulation: B on the matrix cores.  The lower triangle's
+        // 32 x 32 tiles (I >= J) go to the wavefronts in turn; one
+        // v_mfma_f32_32x32x2f32 adds two entries' outer products to a tile:
+        // lane c + 32h supplies column 32I + c (A) and 32J + c (B) of entry h
+        // of the pair, and accumulator register r of lane c + 32h holds tile
+        // element (8 (r / 4) + 4 h + r % 4, c).  c stays on the vector unit.
+        typedef float f32x16 __attribute__((ext_vector_type(16)));
+        const int wave = tid >> 6, lane = tid & 63, col = lane & 31, h = lane >> 5;
+        const int nbk = (K + 31) / 32, ntile = nbk * (nbk + 1) / 2;
+        int ti[3], tj[3];
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const int t = wave + 4 * s;
+            int I = 0;
+            while ((I + 1) * (I + 2) / 2 <= t) ++I;
+            ti[s] = I;
+            tj[s] = t - I * (I + 1) / 2;
+        }
+        f32x16 mac[3];
+#pragma unroll
+        for (int s = 0; s < 3; ++s)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) mac[s][r] = 0.f;
+        for (int64_t c0 = beg; c0 < end; c0 += FOLD_CHUNK) {
+            const int cn = (int)(end - c0 < FOLD_CHUNK ? end - c0 : FOLD_CHUNK);
+            for (int e = tid; e < cn * K; e += 256) Pc[e] = P[c0 * K + e];
+            if (tid < cn) xs[tid] = a.vals[c0 + tid];
+            __syncthreads();
+            for (int j0 = 0; j0 < cn; j0 += 2) {
+                const int e = j0 + h;
+                const bool ein = e < cn;
+#pragma unroll
+                for (int s = 0; s < 3; ++s) {
+                    if (wave + 4 * s >= ntile) continue;   // uniform per wavefront
+                    const int ka = 32 * ti[s] + col, kb = 32 * tj[s] + col;
+                    const bool va = ein && ka < K, vb = ein && kb < K;
+                    const float x = Pc[va ? e * K + ka : 0], y = Pc[vb ? e * K + kb : 0];
+                    mac[s] = __builtin_amdgcn_mfma_f32_32x32x2f32(va ? x : 0.f, vb ? y : 0.f,
+                                                                 mac[s], 0, 0, 0);
+                }
+            }
+            if (tid < K)
+                for (int j = 0; j < cn; ++j) racc += (TA)xs[j] * Pc[j * K + tid];
+            __syncthreads();
+        }
+        TA *out = reinterpret_cast<TA *>(a.gpart) + (int64_t)cidx * fold_gram_stride(K);
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            if (wave + 4 * s >= ntile) continue;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int gi = 32 * ti[s] + 8 * (r / 4) + 4 * h + r % 4, gj = 32 * tj[s] + col;
+                if (gi < K && gj <= gi) out[gi * (gi + 1) / 2 + gj] = mac[s][r];
+            }
+        }
+        if (tid < K) out[K * (K + 1) / 2 + tid] = racc;
+        return;
+    }
     const int nub = (K + 15) / 16;   // row blocks that reach below K
     for (int64_t c0 = beg; c0 < end; c0 += FOLD_CHUNK) {
         const int cn = (int)(end - c0 < FOLD_CHUNK ? end - c0 : FOLD_CHUNK);
