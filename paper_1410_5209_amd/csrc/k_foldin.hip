@@ -82,8 +82,8 @@ template <int PREC>
 __global__ __launch_bounds__(256) void k_fold_gram(FoldArgs a)
 {
     using TA = typename Types<PREC>::TA;
-    __shared__ double xs[FOLD_CHUNK];
-    extern __shared__ double smem[];
+    __shared__ double xs[kFoldChunkEntries];
+    extern __shared__ __align__(16) double smem[];
     const int K = a.K;
     const int cidx = blockIdx.x;
     const int q = a.chunk_req[cidx];
@@ -110,10 +110,13 @@ __global__ __launch_bounds__(256) void k_fold_gram(FoldArgs a)
         typedef float f32x16 __attribute__((ext_vector_type(16)));
         const int wave = tid >> 6, lane = tid & 63, col = lane & 31, h = lane >> 5;
         const int nbk = (K + 31) / 32, ntile = nbk * (nbk + 1) / 2;
+        // tile slots past the last tile compute tile 0 and are not stored,
+        // so the entry loop has no branches (a branch around an accumulator
+        // makes the compiler move it between register files every step)
         int ti[3], tj[3];
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
-            const int t = wave + 4 * s;
+            const int t = wave + 4 * s < ntile ? wave + 4 * s : 0;
             int I = 0;
             while ((I + 1) * (I + 2) / 2 <= t) ++I;
             ti[s] = I;
@@ -124,17 +127,26 @@ __global__ __launch_bounds__(256) void k_fold_gram(FoldArgs a)
         for (int s = 0; s < 3; ++s)
 #pragma unroll
             for (int r = 0; r < 16; ++r) mac[s][r] = 0.f;
-        for (int64_t c0 = beg; c0 < end; c0 += FOLD_CHUNK) {
-            const int cn = (int)(end - c0 < FOLD_CHUNK ? end - c0 : FOLD_CHUNK);
-            for (int e = tid; e < cn * K; e += 256) Pc[e] = P[c0 * K + e];
-            if (tid < cn) xs[tid] = a.vals[c0 + tid];
+        // the whole chunk is staged at once (its loads all in flight together)
+        {
+            const int64_t c0 = beg;
+            const int cn = (int)(end - beg);
+            const TA *src = P + c0 * K;
+            if ((K & 3) == 0) {
+                const float4 *s4 = reinterpret_cast<const float4 *>(src);
+                float4 *d4 = reinterpret_cast<float4 *>(Pc);
+                for (int e = tid; e < cn * K / 4; e += 256) d4[e] = s4[e];
+            } else {
+                for (int e = tid; e < cn * K; e += 256) Pc[e] = src[e];
+            }
+            for (int e = tid; e < cn; e += 256) xs[e] = a.vals[c0 + e];
             __syncthreads();
+#pragma unroll 4
             for (int j0 = 0; j0 < cn; j0 += 2) {
                 const int e = j0 + h;
                 const bool ein = e < cn;
 #pragma unroll
                 for (int s = 0; s < 3; ++s) {
-                    if (wave + 4 * s >= ntile) continue;   // uniform per wavefront
                     const int ka = 32 * ti[s] + col, kb = 32 * tj[s] + col;
                     const bool va = ein && ka < K, vb = ein && kb < K;
                     const float x = Pc[va ? e * K + ka : 0], y = Pc[vb ? e * K + kb : 0];
@@ -144,7 +156,6 @@ __global__ __launch_bounds__(256) void k_fold_gram(FoldArgs a)
             }
             if (tid < K)
                 for (int j = 0; j < cn; ++j) racc += (TA)xs[j] * Pc[j * K + tid];
-            __syncthreads();
         }
         TA *out = reinterpret_cast<TA *>(a.gpart) + (int64_t)cidx * fold_gram_stride(K);
 #pragma unroll
@@ -795,7 +806,17 @@ hipError_t launch_fold_compute(int prec, const FoldArgs &a, int64_t total, int m
         return hipGetLastError();
     }
     if (a.nchunks > 0) {
-        const size_t glds = (size_t)FOLD_CHUNK * a.K * (prec == P_F64 ? 8 : 4);
+        // FP64 stages FOLD_CHUNK entries at a time, FP32 a whole chunk (up to
+        // 128 KB for K = 128, beyond the default 64 KB of dynamic LDS)
+        const size_t glds = prec == P_F64 ? (size_t)FOLD_CHUNK * a.K * 8
+                                          : (size_t)kFoldChunkEntries * a.K * 4;
+        if (glds > 65536) {
+            const void *fn = prec == P_F32 ? (const void *)k_fold_gram<P_F32>
+                                           : (const void *)k_fold_gram<P_BF16>;
+            const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)glds);
+            (void)hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
         if (prec == P_F64) hipLaunchKernelGGL(k_fold_gram<P_F64>, dim3(a.nchunks), dim3(256), glds, st, a);
         else if (prec == P_F32) hipLaunchKernelGGL(k_fold_gram<P_F32>, dim3(a.nchunks), dim3(256), glds, st, a);
         else hipLaunchKernelGGL(k_fold_gram<P_BF16>, dim3(a.nchunks), dim3(256), glds, st, a);
