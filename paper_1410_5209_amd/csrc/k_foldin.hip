@@ -141,7 +141,6 @@ __global__ __launch_bounds__(256) void k_fold_gram(FoldArgs a)
             }
             for (int e = tid; e < cn; e += 256) xs[e] = a.vals[c0 + e];
             __syncthreads();
-#pragma unroll 4
             for (int j0 = 0; j0 < cn; j0 += 2) {
                 const int e = j0 + h;
                 const bool ein = e < cn;
@@ -513,7 +512,9 @@ __global__ __launch_bounds__(256) void k_fold_full(FoldArgs a)
         if (tid == 0 && a.req_status) a.req_status[q] = TF_OK;
         return;
     }
-    // LDS: packed lower triangle L (K(K+1)/2 doubles), rhs (K doubles)
+    // LDS: packed lower triangle L (K(K+1)/2 doubles), then rhs (K doubles
+    // and one spare): rhs is row K of the triangle, so the factorisation
+    // carries c along and leaves y = L^-1 c there
     double *L = smem;
     double *rhs = L + K * (K + 1) / 2;
     sum_chunk_records<TA>(a, q, L, rhs);
@@ -534,8 +535,8 @@ __global__ __launch_bounds__(256) void k_fold_full(FoldArgs a)
     __syncthreads();
     for (int c0 = 0; c0 < K; c0 += kPanel) {
         const int w = K - c0 < kPanel ? K - c0 : kPanel;
-        if (w == kPanel) fold_panel<kPanel>(L, c0, w, K, rdiag, colu, &failed);
-        else fold_panel<0>(L, c0, w, K, rdiag, colu, &failed);
+        if (w == kPanel) fold_panel<kPanel>(L, c0, w, K + 1, rdiag, colu, &failed);
+        else fold_panel<0>(L, c0, w, K + 1, rdiag, colu, &failed);
     }
     if (tid == 0 && a.req_status) a.req_status[q] = failed ? TF_E_NUMERIC : TF_OK;
     if (failed) {
@@ -543,7 +544,9 @@ __global__ __launch_bounds__(256) void k_fold_full(FoldArgs a)
         for (int k = tid; k < K; k += 256) out[k] = 0.0;
         return;
     }
-    // L y = c, then L^T a = y, by one wavefront with the unknowns in
+    // L y = c came with the factorisation: c is row K of the packed
+    // triangle (the rhs array), so the panel rows and trailing updates
+    // turned it into y.  L^T a = y by one wavefront with the unknowns in
     // registers (lane l holds unknowns l and l + 64, and their pivots'
     // reciprocals): each solved value reaches the lanes by a lane read, and
     // every lane subtracts its share; no barriers.  The factor's entries
@@ -554,44 +557,6 @@ __global__ __launch_bounds__(256) void k_fold_full(FoldArgs a)
     const double rd0 = l0 < K ? rdiag[l0] : 0.0, rd1 = l1 < K ? rdiag[l1] : 0.0;
     double y0 = l0 < K ? rhs[l0] : 0.0, y1 = l1 < K ? rhs[l1] : 0.0;
     constexpr int SB = 8;
-    for (int kb = 0; kb < K0; kb += SB) {
-        double a0[SB], a1[SB];
-#pragma unroll
-        for (int t = 0; t < SB; ++t) {
-            const int k = kb + t;
-            const bool v0 = k < K0 && l0 > k && l0 < K, v1 = k < K0 && l1 < K;
-            const double e0 = L[v0 ? tri(l0, k) : 0], e1 = L[v1 ? tri(l1, k) : 0];
-            a0[t] = v0 ? e0 : 0.0;
-            a1[t] = v1 ? e1 : 0.0;
-        }
-#pragma unroll
-        for (int t = 0; t < SB; ++t) {
-            const int k = kb + t;
-            if (k >= K0) continue;
-            const double yk = lane_bcast(y0 * rd0, k);
-            if (l0 == k) y0 = yk;
-            y0 -= a0[t] * yk;
-            y1 -= a1[t] * yk;
-        }
-    }
-    for (int kb = 64; kb < K; kb += SB) {
-        double a1[SB];
-#pragma unroll
-        for (int t = 0; t < SB; ++t) {
-            const int k = kb + t;
-            const bool v1 = k < K && l1 > k && l1 < K;
-            const double e1 = L[v1 ? tri(l1, k) : 0];
-            a1[t] = v1 ? e1 : 0.0;
-        }
-#pragma unroll
-        for (int t = 0; t < SB; ++t) {
-            const int k = kb + t;
-            if (k >= K) continue;
-            const double yk = lane_bcast(y1 * rd1, k - 64);
-            if (l1 == k) y1 = yk;
-            y1 -= a1[t] * yk;
-        }
-    }
     for (int kb = K - 1; kb >= 64; kb -= SB) {
         double b0[SB], b1[SB];
 #pragma unroll
@@ -765,7 +730,7 @@ __global__ __launch_bounds__(256) void k_fold_cdtf_entries(FoldArgs a)
 size_t fold_full_lds(int K, int prec)
 {
     (void)prec;
-    return (size_t)(K * (K + 1) / 2 + K) * 8;
+    return (size_t)(K * (K + 1) / 2 + K + 1) * 8;
 }
 
 hipError_t launch_fold_validate(const FoldArgs &a, int64_t total, const int64_t *dims,
