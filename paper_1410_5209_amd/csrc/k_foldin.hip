@@ -645,7 +645,11 @@ __global__ __launch_bounds__(256) void k_fold_cdtf(FoldArgs a)
     auto bidx = [](int i, int j) { return i >= j ? tri(i, j) : tri(j, i); };
     constexpr int SB = 8;
     for (int s = 0; s < a.sweeps; ++s) {
-        for (int kb = 0; kb < K; kb += SB) {
+        // unrolled over the largest K, so that every lane read names its lane
+        // when compiling
+#pragma unroll
+        for (int kb = 0; kb < kFoldMaxKFull; kb += SB) {
+            if (kb >= K) continue;
             double e0[SB], e1[SB], bk[SB], rk[SB];
 #pragma unroll
             for (int t = 0; t < SB; ++t) {
