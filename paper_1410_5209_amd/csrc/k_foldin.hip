@@ -557,12 +557,16 @@ __global__ __launch_bounds__(256) void k_fold_full(FoldArgs a)
     const double rd0 = l0 < K ? rdiag[l0] : 0.0, rd1 = l1 < K ? rdiag[l1] : 0.0;
     double y0 = l0 < K ? rhs[l0] : 0.0, y1 = l1 < K ? rhs[l1] : 0.0;
     constexpr int SB = 8;
-    for (int kb = K - 1; kb >= 64; kb -= SB) {
+    // both loops unrolled over the largest K, so that every lane read names
+    // its lane when compiling; columns from K up are skipped
+#pragma unroll
+    for (int kb = kFoldMaxKFull - 1; kb >= 64; kb -= SB) {
+        if (kb - SB + 1 >= K) continue;
         double b0[SB], b1[SB];
 #pragma unroll
         for (int t = 0; t < SB; ++t) {
             const int k = kb - t;
-            const bool v0 = k >= 64, v1 = k >= 64 && l1 < k;
+            const bool v0 = k >= 64 && k < K, v1 = v0 && l1 < k;
             const double e0 = L[v0 ? tri(k, l0) : 0], e1 = L[v1 ? tri(k, l1) : 0];
             b0[t] = v0 ? e0 : 0.0;
             b1[t] = v1 ? e1 : 0.0;
@@ -570,26 +574,28 @@ __global__ __launch_bounds__(256) void k_fold_full(FoldArgs a)
 #pragma unroll
         for (int t = 0; t < SB; ++t) {
             const int k = kb - t;
-            if (k < 64) continue;
+            if (k < 64 || k >= K) continue;
             const double ak = lane_bcast(y1 * rd1, k - 64);
             if (l1 == k) y1 = ak;
             y0 -= b0[t] * ak;
             y1 -= b1[t] * ak;
         }
     }
-    for (int kb = K0 - 1; kb >= 0; kb -= SB) {
+#pragma unroll
+    for (int kb = 63; kb >= 0; kb -= SB) {
+        if (kb - SB + 1 >= K0) continue;
         double b0[SB];
 #pragma unroll
         for (int t = 0; t < SB; ++t) {
             const int k = kb - t;
-            const bool v0 = k >= 0 && l0 < k;
+            const bool v0 = k < K0 && l0 < k;
             const double e0 = L[v0 ? tri(k, l0) : 0];
             b0[t] = v0 ? e0 : 0.0;
         }
 #pragma unroll
         for (int t = 0; t < SB; ++t) {
             const int k = kb - t;
-            if (k < 0) continue;
+            if (k >= K0) continue;
             const double ak = lane_bcast(y0 * rd0, k);
             if (l0 == k) y0 = ak;
             y0 -= b0[t] * ak;
